@@ -1,0 +1,254 @@
+/*
+ * soax.h -- C ABI of the MI355X (gfx950) particle-update library.
+ *
+ * A set of n particles has a user schema: an ordered list of named
+ * properties, each with an element type and a dimension (the attribute tuple
+ * of Section 4.1, usage listing: id<int,1>, pos<double,3>, vel<...,3>, ...).
+ * The set keeps two copies of its records side by side in device memory:
+ *
+ *   SoA  one contiguous array per (property, component) -- the "structure of
+ *        arrays" of Section 1 (Listings 2-3), with each vector component in
+ *        its own array as in the benchmark of Section 2;
+ *   AoS  one contiguous array of C records laid out like the struct of
+ *        Section 1 (Listing 1) -- natural C alignment (each member at a
+ *        multiple of its size, record size a multiple of the largest member),
+ *        or packed with no padding.
+ *
+ * All pointers passed to or returned from the library are device pointers
+ * unless a parameter says "host".  Every call that touches the device
+ * enqueues its work on `stream` (a hipStream_t; NULL is the null stream)
+ * and returns without synchronising, except where stated.  The library never
+ * aborts or throws: every function returns a soax_status, and
+ * soax_last_error() gives a thread-local message for the last failure.
+ * Arguments are validated on the host before any device call; an invalid
+ * call changes nothing.
+ */
+#ifndef SOAX_H
+#define SOAX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t soax_status;
+#define SOAX_OK 0
+#define SOAX_E_ARG (-1)    /* null pointer, negative size, non-finite dt/amplitude, bad enum */
+#define SOAX_E_SCHEMA (-2) /* bad dtype/dim/name, duplicate name, missing pos/vel/acc */
+#define SOAX_E_RANGE (-3)  /* n too large for the schema (int32 id, 2^31-1 records) */
+#define SOAX_E_LAYOUT (-4) /* the requested layout's buffer is absent or misaligned */
+#define SOAX_E_OOM (-5)    /* device allocation failed */
+#define SOAX_E_HIP (-6)    /* a HIP runtime call failed (message has hipGetErrorString) */
+#define SOAX_E_STATE (-7)  /* operation not valid for this object (e.g. tuning a batch mid-capture) */
+
+/* Element types. */
+typedef enum { SOAX_I8 = 1, SOAX_U8 = 2, SOAX_I32 = 3, SOAX_I64 = 4, SOAX_F32 = 5, SOAX_F64 = 6 } soax_dtype;
+
+/* One property: `name` (<= 31 chars, unique), element type, dimension 1..3,
+ * and a free one-character descriptive tag (the character argument of the
+ * attribute macro of Section 4.2, which the library stores and ignores). */
+typedef struct {
+  const char* name;
+  int32_t dtype;
+  int32_t dim;
+  char tag;
+} soax_field;
+
+/* Ordered property list (1..32 fields); packed = 0 gives C natural alignment. */
+typedef struct {
+  const soax_field* fields;
+  int32_t nfields;
+  int32_t packed;
+} soax_schema;
+
+typedef enum { SOAX_SOA = 0, SOAX_AOS = 1, SOAX_AOS_NAIVE = 2 } soax_layout;
+
+/*
+ * Integrators.  Properties are found by name: "pos" (dim 3, f32 or f64),
+ * "vel" (dim 3, f32 or f64), "acc" (dim 3, f32 or f64).
+ *   SOAX_EULER      pos += dt * vel                                  (Section 2, eq. (1))
+ *   SOAX_EULER_ACC  pos += dt * vel with the old vel, then vel += dt * acc
+ *   SOAX_RK2_ABC    explicit midpoint in the ABC field
+ *                   u = (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x):
+ *                   xm = x + (dt/2) u(x); x = x + dt u(xm); vel = u(x)   (pos must be f64)
+ * Each step is one full pass over the particles.  A double dt applied to a
+ * float property is evaluated in double and rounded on store (C's usual
+ * arithmetic conversions); no operation is fused into an FMA.
+ */
+typedef enum { SOAX_EULER = 0, SOAX_EULER_ACC = 1, SOAX_RK2_ABC = 2 } soax_integrator;
+
+/* Field amplitudes and the periodic wrap of positions into [0, 2*pi)^3
+ * (wrap = 1 requires f64 positions: x >= L -> x - L, x < 0 -> x + L, and a
+ * sum that rounds to L is stored as 0). */
+typedef struct {
+  double A, B, C;
+  int32_t wrap;
+} soax_params;
+
+typedef struct soax_set soax_set;
+typedef struct soax_batch soax_batch;
+
+/* ---------------------------------------------------------------- schema */
+
+/*
+ * Host only (no device call).  Writes the AoS byte offset of every field
+ * (field_offsets[nfields], may be NULL), the AoS record stride and the SoA
+ * bytes per particle (sum of element size * dim; either may be NULL).
+ */
+soax_status soax_schema_layout(const soax_schema* schema, int64_t* field_offsets,
+                               int64_t* aos_stride, int64_t* soa_bytes);
+
+/* ------------------------------------------------------------ particle sets */
+
+/*
+ * Create a set of n particles on the current HIP device, allocating both
+ * layouts (library-owned; freed by soax_destroy).  Each SoA array starts on
+ * a 256-byte boundary.  Contents are undefined until filled or written.
+ * Errors: ARG (null, n < 0), SCHEMA, RANGE (n > 2^31-1, or an int32/i8/u8
+ * "id" too narrow for n), OOM.
+ */
+soax_status soax_create(const soax_schema* schema, int64_t n, soax_set** out);
+
+/*
+ * Wrap caller-owned device memory (e.g. torch tensors) as a set.  soa_ptrs
+ * holds one pointer per (field, component) in schema order (the array of
+ * component c of field f is at index sum(dims of fields before f) + c); the
+ * whole soa_ptrs argument may be NULL (no SoA copy), and aos_ptr may be NULL
+ * (no AoS copy).  The library never frees bound memory; the caller keeps it
+ * alive until soax_destroy.  Vector (16-byte) kernels are used when every
+ * pointer is 16-byte aligned, scalar ones otherwise.
+ */
+soax_status soax_bind(const soax_schema* schema, int64_t n, void* const* soa_ptrs, void* aos_ptr,
+                      soax_set** out);
+
+/* Free a set (and the memory it owns).  NULL is ignored.  Does not sync. */
+void soax_destroy(soax_set* set);
+
+/* Same as soax_schema_layout for the set's schema. */
+soax_status soax_layout_info(const soax_set* set, int64_t* field_offsets, int64_t* aos_stride,
+                             int64_t* soa_bytes);
+
+/* Device pointers of the set's buffers: array `index` of the SoA copy (see
+ * soax_bind for the numbering) or, with index = -1, the AoS buffer. */
+soax_status soax_buffer(const soax_set* set, int32_t index, void** ptr);
+
+/*
+ * Seeded synthetic fill of every SoA array (SplitMix64, Steele-Lea-Flood
+ * 2014, one counter-based stream per field component; Box-Muller normals):
+ *   id -> i; tag -> raw draw; pos -> U[0, 2pi); vel, acc -> N(0,1);
+ *   mass -> U[0.5, 2); flags -> top 8 bits of a draw; other floats -> U[0,1);
+ *   other integers -> low bytes of a draw.
+ * vel_mode 1 instead sets vel = u(pos) with params' amplitudes.  The AoS
+ * copy is not touched (use soax_soa_to_aos).  Errors: ARG, LAYOUT (no SoA).
+ */
+soax_status soax_fill(soax_set* set, uint64_t seed, int32_t vel_mode, const soax_params* params,
+                      void* stream);
+
+/*
+ * nsteps time steps of `integrator` on one layout: SOAX_SOA (vector loads
+ * per array), SOAX_AOS (records staged through LDS with coalesced 16-byte
+ * accesses), SOAX_AOS_NAIVE (one thread per record, direct per-field
+ * accesses, the uncoalesced pattern of Section 3.2).  Only pos/vel are
+ * written; every other byte keeps its value.  params may be NULL for Euler
+ * steps without wrap.  Errors: ARG, SCHEMA, LAYOUT, HIP.
+ */
+soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double dt, int64_t nsteps,
+                      const soax_params* params, void* stream);
+
+/*
+ * Override the launch shape of soax_step for one layout: block threads
+ * (64..1024, multiple of 64) and particles per thread (1, 2 or 4; SoA only).
+ * 0 restores the default.  Results do not depend on the shape.
+ */
+soax_status soax_step_config(soax_set* set, int32_t layout, int32_t block, int32_t per_thread);
+
+/* Bulk transposes between the two copies, byte-exact; soax_soa_to_aos
+ * writes every padding byte of every record as 0.  Both need both copies. */
+soax_status soax_aos_to_soa(soax_set* set, void* stream);
+soax_status soax_soa_to_aos(soax_set* set, void* stream);
+
+/* Copy record i of one layout (SOAX_SOA or SOAX_AOS) to host memory in AoS
+ * form (stride bytes, padding 0).  Synchronises the null stream. */
+soax_status soax_get_record(const soax_set* set, int32_t layout, int64_t i, void* host_record);
+
+/* ------------------------------------------------ differentiable advection */
+
+/*
+ * RK2 (explicit midpoint) advection of n positions in the ABC field with
+ * amplitudes abc[3] (host), no wrap: x0[d], xT[d] are device arrays of n
+ * doubles (d = 0, 1, 2; xT may alias x0).  The state before steps
+ * 0, k, 2k, ... < nsteps is written to tape[c][d][i] (device,
+ * ceil(nsteps/k) * 3 * n doubles), the checkpoints of the adjoint.
+ */
+soax_status soax_rk2_forward_ckpt(const double* const* x0, double* const* xT, int64_t n,
+                                  const double* abc, double dt, int64_t nsteps, int64_t k,
+                                  double* tape, void* stream);
+
+/*
+ * Discrete adjoint of soax_rk2_forward_ckpt.  Given lamT[d] = dL/dxT (device),
+ * recomputes each k-step segment from its checkpoint and sweeps it backwards
+ * (midpoint-rule transpose: mu = dt J(xm)^T lam; lam += mu + dt/2 J(x)^T mu),
+ * writing grad_x0[d] = dL/dx0 (device, may alias lamT) and grad_abc[3] =
+ * dL/d(A,B,C) (device) summed over particles in a fixed order, so the result
+ * is deterministic and independent of k.
+ */
+soax_status soax_adjoint(const double* tape, const double* const* lamT, int64_t n,
+                         const double* abc, double dt, int64_t nsteps, int64_t k,
+                         double* const* grad_x0, double* grad_abc, void* stream);
+
+/* loss = sum_i sum_d (xT - target)^2 into loss[0] (device) and
+ * lamT = 2 (xT - target) (device; may be NULL); fixed-order reduction. */
+soax_status soax_sqdist_loss(const double* const* xT, const double* const* target, int64_t n,
+                             double* const* lamT, double* loss, void* stream);
+
+/* --------------------------------------------------------------- batching */
+
+/*
+ * A batch of particle sets of one schema (pos f64, vel f32 or f64), stepped
+ * together by RK2 in the ABC field with per-set dt and amplitudes.  The sets
+ * stay owned by the caller and must outlive the batch.
+ */
+soax_status soax_batch_create(soax_set* const* sets, int32_t nsets, soax_batch** out);
+void soax_batch_destroy(soax_batch* batch);
+
+/*
+ * nsteps RK2 steps of every set (wrap on): dt[nsets] and abc[nsets*3] are host arrays.
+ * mode 0: one kernel launch per set per step;
+ * mode 1: one persistent launch per step covering every set;
+ * mode 2: the nsteps persistent launches captured once into a hipGraph
+ *         (cached per nsteps and stream) and replayed with one graph launch.
+ * All modes give bit-identical results.
+ */
+soax_status soax_batch_step(soax_batch* batch, const double* dt, const double* abc, int64_t nsteps,
+                            int32_t mode, void* stream);
+
+/* Set the persistent kernel's shape (block threads, particles per thread,
+ * workgroups per CU); 0 keeps the current value. */
+soax_status soax_batch_config(soax_batch* batch, int32_t block, int32_t per_thread,
+                              int32_t blocks_per_cu);
+soax_status soax_batch_get_config(const soax_batch* batch, int32_t* block, int32_t* per_thread,
+                                  int32_t* blocks_per_cu);
+
+/*
+ * Autotune the persistent kernel's shape by timing candidate shapes on the
+ * batch itself (state saved and restored, so particles do not move) and keep
+ * the fastest.  If cache_path is not NULL the choice is looked up in / added
+ * to that JSON file, keyed by device architecture, set count and particle
+ * count.  Synchronises the device.
+ */
+soax_status soax_batch_tune(soax_batch* batch, const char* cache_path);
+
+/* ------------------------------------------------------------ utilities */
+
+/* dst[0..bytes) = src[0..bytes) with 16-byte loads/stores (16-byte aligned
+ * pointers): the bandwidth probe the step kernels are measured against. */
+soax_status soax_copy(void* dst, const void* src, int64_t bytes, void* stream);
+
+const char* soax_strerror(soax_status status);
+const char* soax_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

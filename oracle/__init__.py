@@ -48,6 +48,7 @@ def lib():
         L.soaxref_draw.argtypes = [ctypes.c_uint64] * 3
         L.soaxref_draw.restype = ctypes.c_uint64
         L.soaxref_fill.argtypes = [sp, i64, ctypes.c_uint64, i32, vp, vp]
+        L.soaxref_fill_range.argtypes = [sp, i64, i64, ctypes.c_uint64, i32, vp, vp]
         L.soaxref_field.argtypes = [vp, vp, vp]
         L.soaxref_field.restype = None
         L.soaxref_step_soa.argtypes = [sp, i64, vp, i32, dbl, i64, vp, i32]
@@ -141,6 +142,16 @@ def fill(schema, n, seed=0, vel_mode=0, abc=None):
     a, ap = _abc(abc)
     _check(lib().soaxref_fill(schema.ref, n, seed, vel_mode, ap if abc is not None else None,
                               _ptrs(arrays)), "soaxref_fill")
+    return arrays
+
+
+def fill_range(schema, first, count, seed=0, vel_mode=0, abc=None):
+    """Fill values of particles first .. first+count-1."""
+    arrays = empty_soa(schema, count)
+    a, ap = _abc(abc)
+    _check(lib().soaxref_fill_range(schema.ref, first, count, seed, vel_mode,
+                                    ap if abc is not None else None, _ptrs(arrays)),
+           "soaxref_fill_range")
     return arrays
 
 

@@ -365,9 +365,14 @@ static void store_real(char* p, int32_t dt, double v) {
  */
 int soaxref_fill(const ref_schema* s, int64_t n, uint64_t seed, int vel_mode, const double* abc,
                  void* const* soa) {
+  return soaxref_fill_range(s, 0, n, seed, vel_mode, abc, soa);
+}
+
+int soaxref_fill_range(const ref_schema* s, int64_t first, int64_t n, uint64_t seed, int vel_mode,
+                       const double* abc, void* const* soa) {
   int rc = check_schema(s);
   if (rc) return rc;
-  if (n < 0 || !soa || (vel_mode != 0 && vel_mode != 1)) return -1;
+  if (n < 0 || first < 0 || !soa || (vel_mode != 0 && vel_mode != 1)) return -1;
   int fpos = find_field(s, "pos"), fvel = find_field(s, "vel");
   if (vel_mode == 1) {
     if (!abc || fpos < 0 || fvel < 0 || s->dims[fpos] != 3 || s->dims[fvel] != 3) return -2;
@@ -385,13 +390,14 @@ int soaxref_fill(const ref_schema* s, int64_t n, uint64_t seed, int vel_mode, co
 #pragma omp parallel for schedule(static)
       for (int64_t i = 0; i < n; ++i) {
         char* p = arr + i * es;
-        uint64_t r = soaxref_draw(seed, st, (uint64_t)i);
+        const uint64_t gi = (uint64_t)(first + i); /* particle index */
+        uint64_t r = soaxref_draw(seed, st, gi);
         if (strcmp(nm, "id") == 0) {
-          if (is_float(dt)) store_real(p, dt, (double)i); else store_int(p, dt, (uint64_t)i);
+          if (is_float(dt)) store_real(p, dt, (double)gi); else store_int(p, dt, gi);
         } else if (strcmp(nm, "pos") == 0 && is_float(dt)) {
           store_real(p, dt, REF_L * unit_open1(r));
         } else if ((strcmp(nm, "vel") == 0 || strcmp(nm, "acc") == 0) && is_float(dt)) {
-          store_real(p, dt, std_normal(seed, st, (uint64_t)i));
+          store_real(p, dt, std_normal(seed, st, gi));
         } else if (strcmp(nm, "mass") == 0 && is_float(dt)) {
           store_real(p, dt, 0.5 + 1.5 * unit_open1(r));
         } else if (strcmp(nm, "flags") == 0 && !is_float(dt)) {

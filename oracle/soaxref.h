@@ -60,6 +60,11 @@ uint64_t soaxref_draw(uint64_t seed, uint64_t stream, uint64_t i);
 int soaxref_fill(const ref_schema* s, int64_t n, uint64_t seed, int vel_mode,
                  const double* abc, void* const* soa);
 
+/* The same values for particles first .. first+n-1 only (soa[a][j] holds
+ * particle first + j): every value depends on the particle index alone. */
+int soaxref_fill_range(const ref_schema* s, int64_t first, int64_t n, uint64_t seed, int vel_mode,
+                       const double* abc, void* const* soa);
+
 /* ABC velocity field u(x) for one point. */
 void soaxref_field(const double* abc, const double* x, double* u);
 

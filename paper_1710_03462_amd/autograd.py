@@ -1,0 +1,83 @@
+"""Differentiable RK2 advection in the ABC field.
+
+RK2Advect.apply(pos0, abc, dt, nsteps, k) advances positions pos0 ([3, n]
+float64, on the GPU) by nsteps explicit-midpoint steps in the field with
+amplitudes abc ([3] float64) and returns the final positions.  The forward
+kernel keeps a checkpoint every k steps; backward runs the library's
+discrete-adjoint kernel, which recomputes each k-step segment from its
+checkpoint and sweeps it backwards, giving dL/dpos0 and dL/d(A, B, C).
+"""
+import ctypes
+
+import torch
+
+from ._lib import check, lib
+from .particles import current_stream
+
+
+def _rows(t):
+    """Row pointers of a contiguous [3, n] float64 tensor."""
+    assert t.dtype == torch.float64 and t.is_contiguous() and t.shape[0] == 3
+    return (ctypes.c_void_p * 3)(*[t[d].data_ptr() for d in range(3)])
+
+
+def _host3(abc):
+    vals = [float(v) for v in abc.detach().to("cpu", torch.float64).reshape(3)]
+    return (ctypes.c_double * 3)(*vals)
+
+
+def forward_ckpt(pos0, abc_host, dt, nsteps, k):
+    """(xT, tape) with the library's checkpointing forward kernel."""
+    n = pos0.shape[1]
+    xT = torch.empty_like(pos0)
+    nck = max(1, -(-int(nsteps) // int(k)))
+    tape = torch.empty((nck, 3, max(n, 1)), dtype=torch.float64, device=pos0.device)
+    check(lib().soax_rk2_forward_ckpt(_rows(pos0), _rows(xT), n, abc_host, float(dt), int(nsteps),
+                                      int(k), ctypes.c_void_p(tape.data_ptr()), current_stream()),
+          "soax_rk2_forward_ckpt")
+    return xT, tape
+
+
+def adjoint(tape, lamT, abc_host, dt, nsteps, k):
+    """(dL/dx0, dL/d(A,B,C)) for the seed lamT = dL/dxT."""
+    n = lamT.shape[1]
+    gx = torch.empty_like(lamT)
+    gabc = torch.empty(3, dtype=torch.float64, device=lamT.device)
+    check(lib().soax_adjoint(ctypes.c_void_p(tape.data_ptr()), _rows(lamT), n, abc_host, float(dt),
+                             int(nsteps), int(k), _rows(gx), ctypes.c_void_p(gabc.data_ptr()),
+                             current_stream()), "soax_adjoint")
+    return gx, gabc
+
+
+def sqdist_loss(xT, target, want_grad=True):
+    """(sum (xT - target)^2 as a 1-element tensor, 2 (xT - target) or None)."""
+    n = xT.shape[1]
+    loss = torch.empty(1, dtype=torch.float64, device=xT.device)
+    lam = torch.empty_like(xT) if want_grad else None
+    check(lib().soax_sqdist_loss(_rows(xT), _rows(target), n, _rows(lam) if want_grad else None,
+                                 ctypes.c_void_p(loss.data_ptr()), current_stream()),
+          "soax_sqdist_loss")
+    return loss, lam
+
+
+class RK2Advect(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, pos0, abc, dt, nsteps, k):
+        pos0 = pos0.contiguous()
+        abc_host = _host3(abc)
+        xT, tape = forward_ckpt(pos0, abc_host, dt, nsteps, k)
+        ctx.save_for_backward(tape)
+        ctx.abc_host, ctx.dt, ctx.nsteps, ctx.k = abc_host, dt, nsteps, k
+        ctx.abc_device = abc.device
+        return xT
+
+    @staticmethod
+    def backward(ctx, grad_xT):
+        (tape,) = ctx.saved_tensors
+        lam = grad_xT.contiguous().to(torch.float64)
+        gx, gabc = adjoint(tape, lam, ctx.abc_host, ctx.dt, ctx.nsteps, ctx.k)
+        return gx, gabc.to(ctx.abc_device), None, None, None
+
+
+def rk2_advect(pos0, abc, dt, nsteps, k=20):
+    return RK2Advect.apply(pos0, abc, dt, nsteps, k)

@@ -1,0 +1,245 @@
+// k_adjoint.hip -- gfx950 kernels for differentiating RK2 advection in the
+// ABC field: forward with checkpoints, the discrete adjoint with
+// recomputation, and a squared-distance loss.
+//
+// One thread owns one particle for the whole time loop (the state stays in
+// registers).  The adjoint walks the checkpoint segments backwards; for each
+// segment it recomputes the states from the checkpoint into a register array
+// indexed by compile-time constants (fully unrolled loops, so the array never
+// touches scratch memory) and sweeps them backwards.  Segments longer than
+// the register array are split into sub-segments, each recomputed from the
+// checkpoint.  Parameter gradients are summed per particle in reverse step
+// order, then over particles by a fixed-shape tree (per workgroup, then one
+// final workgroup), so results are deterministic and do not depend on k.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_math.h"
+#include "launch.h"
+
+namespace soax {
+
+namespace {
+
+constexpr int kRedBlock = 256;  // workgroup size of every reducing kernel
+
+
+
+__global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const Abc p = to_abc(a.abc);
+  double x = a.x0[0][i], y = a.x0[1][i], z = a.x0[2][i];
+  double* tp = a.tape + i;
+  const int64_t n = a.n;
+  int64_t until_ckpt = 0;
+  for (int64_t s = 0; s < a.nsteps; ++s) {
+    if (until_ckpt == 0) {
+      tp[0] = x;
+      tp[n] = y;
+      tp[2 * n] = z;
+      tp += 3 * n;
+      until_ckpt = a.k;
+    }
+    --until_ckpt;
+    rk2_midpoint(p, a.dt, x, y, z);
+  }
+  a.xT[0][i] = x;
+  a.xT[1][i] = y;
+  a.xT[2][i] = z;
+}
+
+// Reverse one midpoint step taken from state (x, y, z).  With
+// xm = x + (dt/2) u(x) and x+ = x + dt u(xm):
+//   mu  = dt J(xm)^T lam+
+//   g  += dt G(xm)^T lam+ + (dt/2) G(x)^T mu
+//   lam = lam+ + mu + (dt/2) J(x)^T mu
+// where J = du/dx and G = du/d(A,B,C).
+__device__ __forceinline__ void rk2_reverse(const Abc& p, double dt, double x, double y, double z,
+                                            double& l0, double& l1, double& l2, double& g0,
+                                            double& g1, double& g2) {
+  double sx, cx, sy, cy, sz, cz;
+  sincos_f64(x, &sx, &cx);
+  sincos_f64(y, &sy, &cy);
+  sincos_f64(z, &sz, &cz);
+  const double h = 0.5 * dt;
+  const double k0 = p.A * sz + p.C * cy;
+  const double k1 = p.B * sx + p.A * cz;
+  const double k2 = p.C * sy + p.B * cx;
+  double smx, cmx, smy, cmy, smz, cmz;
+  sincos_f64(x + h * k0, &smx, &cmx);
+  sincos_f64(y + h * k1, &smy, &cmy);
+  sincos_f64(z + h * k2, &smz, &cmz);
+  // J(xm)^T lam
+  const double t0 = (p.B * cmx) * l1 - (p.B * smx) * l2;
+  const double t1 = (p.C * cmy) * l2 - (p.C * smy) * l0;
+  const double t2 = (p.A * cmz) * l0 - (p.A * smz) * l1;
+  const double m0 = dt * t0, m1 = dt * t1, m2 = dt * t2;
+  // G(xm)^T lam and G(x)^T mu
+  const double qa = smz * l0 + cmz * l1, qb = smx * l1 + cmx * l2, qc = cmy * l0 + smy * l2;
+  const double ra = sz * m0 + cz * m1, rb = sx * m1 + cx * m2, rc = cy * m0 + sy * m2;
+  g0 = g0 + (dt * qa + h * ra);
+  g1 = g1 + (dt * qb + h * rb);
+  g2 = g2 + (dt * qc + h * rc);
+  // J(x)^T mu
+  const double s0 = (p.B * cx) * m1 - (p.B * sx) * m2;
+  const double s1 = (p.C * cy) * m2 - (p.C * sy) * m0;
+  const double s2 = (p.A * cz) * m0 - (p.A * sz) * m1;
+  l0 = l0 + m0 + h * s0;
+  l1 = l1 + m1 + h * s1;
+  l2 = l2 + m2 + h * s2;
+}
+
+// Sum v over the workgroup (kRedBlock threads) in a fixed tree order.
+__device__ __forceinline__ void block_sum3(double v0, double v1, double v2, double* out3) {
+  __shared__ double red[3][kRedBlock];
+  const int t = threadIdx.x;
+  red[0][t] = v0;
+  red[1][t] = v1;
+  red[2][t] = v2;
+  __syncthreads();
+  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      red[0][t] += red[0][t + s];
+      red[1][t] += red[1][t + s];
+      red[2][t] += red[2][t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out3[0] = red[0][0];
+    out3[1] = red[1][0];
+    out3[2] = red[2][0];
+  }
+}
+
+// KM: states held in registers per (sub-)segment.
+template <int KM>
+__global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const Abc p = to_abc(a.abc);
+  const double dt = a.dt;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  if (i < a.n) {
+    const int64_t n = a.n;
+    double l0 = a.lam[0][i], l1 = a.lam[1][i], l2 = a.lam[2][i];
+    const int64_t nseg = (a.nsteps + a.k - 1) / a.k;
+    for (int64_t c = nseg - 1; c >= 0; --c) {
+      const int64_t len = min(a.k, a.nsteps - c * a.k);
+      const double* cp = a.tape + (c * 3) * n + i;
+      const int64_t nsub = (len + KM - 1) / KM;
+      for (int64_t q = nsub - 1; q >= 0; --q) {
+        double x = cp[0], y = cp[n], z = cp[2 * n];
+        for (int64_t s = 0; s < q * KM; ++s) rk2_midpoint(p, dt, x, y, z);
+        const int m = static_cast<int>(min(static_cast<int64_t>(KM), len - q * KM));
+        double sx[KM], sy[KM], sz[KM];
+#pragma unroll
+        for (int j = 0; j < KM; ++j) {
+          if (j < m) {
+            sx[j] = x;
+            sy[j] = y;
+            sz[j] = z;
+            if (j + 1 < m) rk2_midpoint(p, dt, x, y, z);
+          }
+        }
+#pragma unroll
+        for (int j = KM - 1; j >= 0; --j) {
+          if (j < m) rk2_reverse(p, dt, sx[j], sy[j], sz[j], l0, l1, l2, g0, g1, g2);
+        }
+      }
+    }
+    a.gx[0][i] = l0;
+    a.gx[1][i] = l1;
+    a.gx[2][i] = l2;
+  }
+  block_sum3(g0, g1, g2, a.partial + 3 * static_cast<int64_t>(blockIdx.x));
+}
+
+// One workgroup: out[d] = sum_b partial[3b + d], each thread summing a fixed
+// strided slice in order, then the fixed tree.
+__global__ __launch_bounds__(kRedBlock) void final_sum3_kernel(const double* __restrict__ partial,
+                                                               int64_t nparts,
+                                                               double* __restrict__ out) {
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int64_t b = threadIdx.x; b < nparts; b += kRedBlock) {
+    v0 += partial[3 * b];
+    v1 += partial[3 * b + 1];
+    v2 += partial[3 * b + 2];
+  }
+  block_sum3(v0, v1, v2, out);
+}
+
+// Like final_sum3_kernel but the sum of the three components goes to out[0].
+__global__ __launch_bounds__(kRedBlock) void final_sum1_kernel(const double* __restrict__ partial,
+                                                               int64_t nparts,
+                                                               double* __restrict__ out) {
+  __shared__ double tot[3];
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int64_t b = threadIdx.x; b < nparts; b += kRedBlock) {
+    v0 += partial[3 * b];
+    v1 += partial[3 * b + 1];
+    v2 += partial[3 * b + 2];
+  }
+  block_sum3(v0, v1, v2, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = (tot[0] + tot[1]) + tot[2];
+}
+
+__global__ __launch_bounds__(kRedBlock) void sqdist_kernel(LossArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+  if (i < a.n) {
+    e0 = a.xT[0][i] - a.target[0][i];
+    e1 = a.xT[1][i] - a.target[1][i];
+    e2 = a.xT[2][i] - a.target[2][i];
+    if (a.lam[0]) {
+      a.lam[0][i] = 2.0 * e0;
+      a.lam[1][i] = 2.0 * e1;
+      a.lam[2][i] = 2.0 * e2;
+    }
+  }
+  block_sum3(e0 * e0, e1 * e1, e2 * e2, a.partial + 3 * static_cast<int64_t>(blockIdx.x));
+}
+
+}  // namespace
+
+hipError_t launch_rk2_forward_ckpt(const CkptArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const int64_t grid = (a.n + 255) / 256;
+  hipLaunchKernelGGL(rk2_ckpt_kernel, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+int64_t adjoint_partials(int64_t n) { return (n + kRedBlock - 1) / kRedBlock; }
+
+hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s) {
+  const int64_t grid = adjoint_partials(a.n);
+  if (grid > 0) {
+    if (a.k <= 8)
+      hipLaunchKernelGGL((adjoint_kernel<8>), dim3(grid), dim3(kRedBlock), 0, s, a);
+    else if (a.k <= 20)
+      hipLaunchKernelGGL((adjoint_kernel<20>), dim3(grid), dim3(kRedBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((adjoint_kernel<32>), dim3(grid), dim3(kRedBlock), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(final_sum3_kernel, dim3(1), dim3(kRedBlock), 0, s, a.partial, grid,
+                     a.grad_abc);
+  return hipGetLastError();
+}
+
+int64_t loss_partials(int64_t n) { return (n + kRedBlock - 1) / kRedBlock; }
+
+hipError_t launch_sqdist_loss(const LossArgs& a, hipStream_t s) {
+  const int64_t grid = loss_partials(a.n);
+  if (grid > 0) {
+    hipLaunchKernelGGL(sqdist_kernel, dim3(grid), dim3(kRedBlock), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(final_sum1_kernel, dim3(1), dim3(kRedBlock), 0, s, a.partial, grid, a.loss);
+  return hipGetLastError();
+}
+
+}  // namespace soax

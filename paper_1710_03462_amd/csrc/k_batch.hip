@@ -1,0 +1,110 @@
+// k_batch.hip -- one persistent launch advancing many particle sets of
+// uneven sizes by one RK2 step each, every set with its own dt and field
+// amplitudes.
+//
+// The sets are cut into tiles of `tile` particles (the last tile of a set may
+// be short) and listed back to back; a grid of a few workgroups per compute
+// unit walks the list with a grid stride, reading each tile's set from a
+// device table.  Small sets therefore share the machine instead of each
+// paying for a launch of its own.  The per-particle arithmetic is the same
+// inline function the single-set kernels use, so a set advanced here is
+// bit-identical to the same set advanced alone.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_math.h"
+#include "launch.h"
+
+namespace soax {
+
+namespace {
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec(const T* p, T (&v)[VEC]) {
+  if constexpr (VEC == 1) {
+    v[0] = *p;
+  } else {
+    __builtin_memcpy(v, __builtin_assume_aligned(p, run_align<T, VEC>()), sizeof(T) * VEC);
+  }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec(T* p, const T (&v)[VEC]) {
+  if constexpr (VEC == 1) {
+    *p = v[0];
+  } else {
+    __builtin_memcpy(__builtin_assume_aligned(p, run_align<T, VEC>()), v, sizeof(T) * VEC);
+  }
+}
+
+template <typename VT, int PPT>
+__global__ __launch_bounds__(1024) void batch_rk2_kernel(BatchLaunch b) {
+  for (int64_t t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
+    const BatchSet& S = b.sets[b.tile_set[t]];
+    const Abc p{S.A, S.B, S.C};
+    const double dt = S.dt;
+    const int64_t i0 = (t - S.tile_begin) * b.tile + static_cast<int64_t>(threadIdx.x) * PPT;
+    double* px = S.pos[0];
+    double* py = S.pos[1];
+    double* pz = S.pos[2];
+    VT* vx = static_cast<VT*>(S.vel[0]);
+    VT* vy = static_cast<VT*>(S.vel[1]);
+    VT* vz = static_cast<VT*>(S.vel[2]);
+    if (i0 + PPT <= S.n) {
+      double x[PPT], y[PPT], z[PPT];
+      VT u[PPT], v[PPT], w[PPT];
+      load_vec<double, PPT>(px + i0, x);
+      load_vec<double, PPT>(py + i0, y);
+      load_vec<double, PPT>(pz + i0, z);
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        u[j] = v[j] = w[j] = VT(0);
+        update_particle<kRk2Abc, double, VT>(x[j], y[j], z[j], u[j], v[j], w[j], VT(0), VT(0),
+                                             VT(0), dt, p, 1);
+      }
+      store_vec<double, PPT>(px + i0, x);
+      store_vec<double, PPT>(py + i0, y);
+      store_vec<double, PPT>(pz + i0, z);
+      store_vec<VT, PPT>(vx + i0, u);
+      store_vec<VT, PPT>(vy + i0, v);
+      store_vec<VT, PPT>(vz + i0, w);
+    } else {
+      for (int64_t i = i0; i < S.n; ++i) {
+        double x = px[i], y = py[i], z = pz[i];
+        VT u = VT(0), v = VT(0), w = VT(0);
+        update_particle<kRk2Abc, double, VT>(x, y, z, u, v, w, VT(0), VT(0), VT(0), dt, p, 1);
+        px[i] = x;
+        py[i] = y;
+        pz[i] = z;
+        vx[i] = u;
+        vy[i] = v;
+        vz[i] = w;
+      }
+    }
+  }
+}
+
+template <typename VT>
+hipError_t batch_t(const BatchLaunch& b, hipStream_t s) {
+  switch (b.per_thread) {
+    case 1:
+      hipLaunchKernelGGL((batch_rk2_kernel<VT, 1>), dim3(b.grid), dim3(b.block), 0, s, b);
+      break;
+    case 2:
+      hipLaunchKernelGGL((batch_rk2_kernel<VT, 2>), dim3(b.grid), dim3(b.block), 0, s, b);
+      break;
+    default:
+      hipLaunchKernelGGL((batch_rk2_kernel<VT, 4>), dim3(b.grid), dim3(b.block), 0, s, b);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_batch_rk2(const BatchLaunch& b, hipStream_t s) {
+  if (b.ntiles == 0) return hipSuccess;
+  return b.vel_t == kF64 ? batch_t<double>(b, s) : batch_t<float>(b, s);
+}
+
+}  // namespace soax

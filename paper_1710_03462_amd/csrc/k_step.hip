@@ -1,0 +1,584 @@
+// k_step.hip -- gfx950 kernels for the per-particle time step in both
+// layouts, the bulk AoS<->SoA transposes, the seeded fill and the copy probe.
+//
+// The step (Section 2, eq. (1) and its RK2 / acceleration variants) is a
+// streaming read-modify-write with no reuse inside a step, so the kernels are
+// shaped for HBM, not for the matrix cores:
+//  * SoA: each thread owns `VEC` consecutive particles and moves every array
+//    it touches with 16-byte loads and stores, so a wave covers 1 KiB of each
+//    array per instruction; untouched arrays (id, mass, ...) are never read
+//    (Section 2: "data that is not used in the execution loop will not be
+//    loaded").
+//  * AoS: a workgroup stages a tile of whole records through LDS with
+//    coalesced 16-byte accesses, updates the records in LDS and writes the
+//    tile back, so the only waste is the bytes of unused fields, not the
+//    uncoalesced pattern of Section 3.2; the naive kernel keeps that pattern
+//    (one thread per record, direct per-field accesses) for comparison.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_math.h"
+#include "launch.h"
+
+namespace soax {
+
+namespace {
+
+constexpr int kLdsBudget = 48 * 1024;  // bytes of LDS staging per workgroup
+
+
+
+// ------------------------------------------------------------ SoA step
+
+// Load / store VEC consecutive elements (16-byte aligned when VEC > 1).
+template <typename T, int VEC>
+__device__ __forceinline__ void load_run(const T* p, T (&v)[VEC]) {
+  if constexpr (VEC == 1) {
+    v[0] = *p;
+  } else {
+    const T* q = static_cast<const T*>(__builtin_assume_aligned(p, run_align<T, VEC>()));
+    __builtin_memcpy(v, q, sizeof(T) * VEC);
+  }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_run(T* p, const T (&v)[VEC]) {
+  if constexpr (VEC == 1) {
+    *p = v[0];
+  } else {
+    T* q = static_cast<T*>(__builtin_assume_aligned(p, run_align<T, VEC>()));
+    __builtin_memcpy(q, v, sizeof(T) * VEC);
+  }
+}
+
+template <int INTEG, typename PT, typename VT, int VEC>
+__global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t i0 = t * VEC;
+  if (i0 >= a.n) return;
+  const Abc p = to_abc(a.abc);
+  PT* px = static_cast<PT*>(a.pos[0]);
+  PT* py = static_cast<PT*>(a.pos[1]);
+  PT* pz = static_cast<PT*>(a.pos[2]);
+  VT* vx = static_cast<VT*>(a.vel[0]);
+  VT* vy = static_cast<VT*>(a.vel[1]);
+  VT* vz = static_cast<VT*>(a.vel[2]);
+  const VT* ax = static_cast<const VT*>(a.acc[0]);
+  const VT* ay = static_cast<const VT*>(a.acc[1]);
+  const VT* az = static_cast<const VT*>(a.acc[2]);
+  constexpr bool kReadsVel = INTEG != kRk2Abc;  // RK2 overwrites vel without reading it
+
+  if (i0 + VEC <= a.n) {
+    PT x[VEC], y[VEC], z[VEC];
+    VT u[VEC], v[VEC], w[VEC];
+    VT ga[VEC], gb[VEC], gc[VEC];
+    load_run<PT, VEC>(px + i0, x);
+    load_run<PT, VEC>(py + i0, y);
+    load_run<PT, VEC>(pz + i0, z);
+    if constexpr (kReadsVel) {
+      load_run<VT, VEC>(vx + i0, u);
+      load_run<VT, VEC>(vy + i0, v);
+      load_run<VT, VEC>(vz + i0, w);
+    }
+    if constexpr (INTEG == kEulerAcc) {
+      load_run<VT, VEC>(ax + i0, ga);
+      load_run<VT, VEC>(ay + i0, gb);
+      load_run<VT, VEC>(az + i0, gc);
+    } else {
+#pragma unroll
+      for (int j = 0; j < VEC; ++j) ga[j] = gb[j] = gc[j] = VT(0);
+    }
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+      if constexpr (!kReadsVel) u[j] = v[j] = w[j] = VT(0);
+      update_particle<INTEG, PT, VT>(x[j], y[j], z[j], u[j], v[j], w[j], ga[j], gb[j], gc[j],
+                                     a.dt, p, a.wrap);
+    }
+    store_run<PT, VEC>(px + i0, x);
+    store_run<PT, VEC>(py + i0, y);
+    store_run<PT, VEC>(pz + i0, z);
+    if constexpr (INTEG != kEuler) {
+      store_run<VT, VEC>(vx + i0, u);
+      store_run<VT, VEC>(vy + i0, v);
+      store_run<VT, VEC>(vz + i0, w);
+    }
+  } else {
+    for (int64_t i = i0; i < a.n; ++i) {
+      PT x = px[i], y = py[i], z = pz[i];
+      VT u = kReadsVel ? vx[i] : VT(0), v = kReadsVel ? vy[i] : VT(0),
+         w = kReadsVel ? vz[i] : VT(0);
+      VT g0 = VT(0), g1 = VT(0), g2 = VT(0);
+      if constexpr (INTEG == kEulerAcc) {
+        g0 = ax[i];
+        g1 = ay[i];
+        g2 = az[i];
+      }
+      update_particle<INTEG, PT, VT>(x, y, z, u, v, w, g0, g1, g2, a.dt, p, a.wrap);
+      px[i] = x;
+      py[i] = y;
+      pz[i] = z;
+      if constexpr (INTEG != kEuler) {
+        vx[i] = u;
+        vy[i] = v;
+        vz[i] = w;
+      }
+    }
+  }
+}
+
+template <int INTEG, typename PT, typename VT>
+hipError_t soa_step_vec(int vec, int block, const SoaStepArgs& a, hipStream_t s) {
+  const int64_t threads = (a.n + vec - 1) / vec;
+  const int64_t grid = (threads + block - 1) / block;
+  if (grid == 0) return hipSuccess;
+  switch (vec) {
+    case 1:
+      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 1>), dim3(grid), dim3(block), 0, s, a);
+      break;
+    case 2:
+      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 2>), dim3(grid), dim3(block), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 4>), dim3(grid), dim3(block), 0, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- AoS element access
+
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ T rec_load(const char* p) {
+  if constexpr (ALIGNED) {
+    return *reinterpret_cast<const T*>(p);
+  } else {
+    T v;
+    __builtin_memcpy(&v, p, sizeof(T));
+    return v;
+  }
+}
+
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ void rec_store(char* p, T v) {
+  if constexpr (ALIGNED) {
+    *reinterpret_cast<T*>(p) = v;
+  } else {
+    __builtin_memcpy(p, &v, sizeof(T));
+  }
+}
+
+// Update the record at `rec` (in LDS or global memory) in place.
+template <int INTEG, typename PT, typename VT, bool ALIGNED>
+__device__ __forceinline__ void update_record(char* rec, const AosStepArgs& a, const Abc& p) {
+  char* P = rec + a.off_pos;
+  char* V = rec + a.off_vel;
+  PT x = rec_load<PT, ALIGNED>(P), y = rec_load<PT, ALIGNED>(P + sizeof(PT)),
+     z = rec_load<PT, ALIGNED>(P + 2 * sizeof(PT));
+  VT u = VT(0), v = VT(0), w = VT(0), g0 = VT(0), g1 = VT(0), g2 = VT(0);
+  if constexpr (INTEG != kRk2Abc) {
+    u = rec_load<VT, ALIGNED>(V);
+    v = rec_load<VT, ALIGNED>(V + sizeof(VT));
+    w = rec_load<VT, ALIGNED>(V + 2 * sizeof(VT));
+  }
+  if constexpr (INTEG == kEulerAcc) {
+    const char* G = rec + a.off_acc;
+    g0 = rec_load<VT, ALIGNED>(G);
+    g1 = rec_load<VT, ALIGNED>(G + sizeof(VT));
+    g2 = rec_load<VT, ALIGNED>(G + 2 * sizeof(VT));
+  }
+  update_particle<INTEG, PT, VT>(x, y, z, u, v, w, g0, g1, g2, a.dt, p, a.wrap);
+  rec_store<PT, ALIGNED>(P, x);
+  rec_store<PT, ALIGNED>(P + sizeof(PT), y);
+  rec_store<PT, ALIGNED>(P + 2 * sizeof(PT), z);
+  if constexpr (INTEG != kEuler) {
+    rec_store<VT, ALIGNED>(V, u);
+    rec_store<VT, ALIGNED>(V + sizeof(VT), v);
+    rec_store<VT, ALIGNED>(V + 2 * sizeof(VT), w);
+  }
+}
+
+// Copy `nbytes` from global `g` (16-byte aligned) into LDS with 16-byte
+// accesses, consecutive lanes on consecutive chunks; the remainder bytewise.
+__device__ __forceinline__ void stage_in(char* lds, const char* g, int nbytes) {
+  const int nchunk = nbytes >> 4;
+  const uint4* src = reinterpret_cast<const uint4*>(g);
+  uint4* dst = reinterpret_cast<uint4*>(lds);
+  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) dst[c] = src[c];
+  for (int b = (nchunk << 4) + threadIdx.x; b < nbytes; b += blockDim.x) lds[b] = g[b];
+}
+
+__device__ __forceinline__ void stage_out(char* g, const char* lds, int nbytes) {
+  const int nchunk = nbytes >> 4;
+  const uint4* src = reinterpret_cast<const uint4*>(lds);
+  uint4* dst = reinterpret_cast<uint4*>(g);
+  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) dst[c] = src[c];
+  for (int b = (nchunk << 4) + threadIdx.x; b < nbytes; b += blockDim.x) g[b] = lds[b];
+}
+
+// ------------------------------------------------------------- AoS steps
+
+template <int INTEG, typename PT, typename VT, bool ALIGNED>
+__global__ __launch_bounds__(1024) void aos_step_kernel(AosStepArgs a, int tile) {
+  extern __shared__ uint4 lds_u4[];
+  char* lds = reinterpret_cast<char*>(lds_u4);
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * tile;
+  const int nrec = static_cast<int>(min(static_cast<int64_t>(tile), a.n - r0));
+  char* g = a.aos + r0 * a.stride;
+  const int nbytes = nrec * a.stride;
+  stage_in(lds, g, nbytes);
+  __syncthreads();
+  const Abc p = to_abc(a.abc);
+  for (int r = threadIdx.x; r < nrec; r += blockDim.x)
+    update_record<INTEG, PT, VT, ALIGNED>(lds + r * a.stride, a, p);
+  __syncthreads();
+  stage_out(g, lds, nbytes);
+}
+
+template <int INTEG, typename PT, typename VT, bool ALIGNED>
+__global__ __launch_bounds__(1024) void aos_naive_kernel(AosStepArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  update_record<INTEG, PT, VT, ALIGNED>(a.aos + i * a.stride, a, to_abc(a.abc));
+}
+
+template <int INTEG, typename PT, typename VT>
+hipError_t aos_step_t(bool aligned, bool naive, int block, const AosStepArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  if (naive) {
+    const int64_t grid = (a.n + block - 1) / block;
+    if (aligned)
+      hipLaunchKernelGGL((aos_naive_kernel<INTEG, PT, VT, true>), dim3(grid), dim3(block), 0, s, a);
+    else
+      hipLaunchKernelGGL((aos_naive_kernel<INTEG, PT, VT, false>), dim3(grid), dim3(block), 0, s, a);
+  } else {
+    const int tile = aos_tile_records(a.stride, block);
+    const int64_t grid = (a.n + tile - 1) / tile;
+    const size_t lds = (static_cast<size_t>(tile) * a.stride + 15) & ~static_cast<size_t>(15);
+    if (aligned)
+      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, true>), dim3(grid), dim3(block), lds, s,
+                         a, tile);
+    else
+      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, false>), dim3(grid), dim3(block), lds, s,
+                         a, tile);
+  }
+  return hipGetLastError();
+}
+
+template <int INTEG>
+hipError_t aos_dispatch(int pos_t, int vel_t, bool aligned, bool naive, int block,
+                        const AosStepArgs& a, hipStream_t s) {
+  if (pos_t == kF64 && vel_t == kF32) return aos_step_t<INTEG, double, float>(aligned, naive, block, a, s);
+  if (pos_t == kF64 && vel_t == kF64) return aos_step_t<INTEG, double, double>(aligned, naive, block, a, s);
+  if constexpr (INTEG != kRk2Abc) {
+    if (pos_t == kF32 && vel_t == kF32) return aos_step_t<INTEG, float, float>(aligned, naive, block, a, s);
+    if (pos_t == kF32 && vel_t == kF64) return aos_step_t<INTEG, float, double>(aligned, naive, block, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------- transposes
+
+// Copy `es` bytes (1, 4 or 8).
+template <bool ALIGNED>
+__device__ __forceinline__ void copy_elem(char* dst, const char* src, int es) {
+  if constexpr (ALIGNED) {
+    if (es == 8)
+      *reinterpret_cast<uint64_t*>(dst) = *reinterpret_cast<const uint64_t*>(src);
+    else if (es == 4)
+      *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(src);
+    else
+      *dst = *src;
+  } else {
+    for (int b = 0; b < es; ++b) dst[b] = src[b];
+  }
+}
+
+// Walk the tile's SoA side in 16-byte chunks: chunk w belongs to the array
+// `arr` with sum_{b<arr} tile*es_b/16 <= w, and covers 16/es elements.
+struct ChunkCursor {
+  int arr = 0;
+  int base = 0;
+};
+
+__device__ __forceinline__ bool seek_chunk(const XposeArgs& t, int tile, int w, ChunkCursor& c) {
+  while (c.arr < t.narrays) {
+    const int nch = (tile * t.es[c.arr]) >> 4;
+    if (w < c.base + nch) return true;
+    c.base += nch;
+    ++c.arr;
+  }
+  return false;
+}
+
+template <bool ALIGNED>
+__global__ __launch_bounds__(256) void aos_to_soa_kernel(const XposeArgs* __restrict__ tp,
+                                                         int tile) {
+  extern __shared__ uint4 lds_u4[];
+  char* lds = reinterpret_cast<char*>(lds_u4);
+  const XposeArgs& t = *tp;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * tile;
+  const int nrec = static_cast<int>(min(static_cast<int64_t>(tile), t.n - r0));
+  const int stride = t.stride;
+  stage_in(lds, t.aos + r0 * stride, nrec * stride);
+  __syncthreads();
+  if (nrec == tile) {
+    ChunkCursor c;
+    for (int w = threadIdx.x; seek_chunk(t, tile, w, c); w += blockDim.x) {
+      const int es = t.es[c.arr];
+      const int per = 16 / es;
+      const int e0 = (w - c.base) * per;
+      const char* src = lds + e0 * stride + t.off[c.arr];
+      uint4 val;
+      char* vb = reinterpret_cast<char*>(&val);
+      for (int q = 0; q < per; ++q) copy_elem<ALIGNED>(vb + q * es, src + q * stride, es);
+      *reinterpret_cast<uint4*>(t.soa[c.arr] + (r0 + e0) * es) = val;
+    }
+  } else {
+    for (int w = threadIdx.x; w < nrec * t.narrays; w += blockDim.x) {
+      const int arr = w / nrec, e = w - arr * nrec;
+      const int es = t.es[arr];
+      copy_elem<ALIGNED>(t.soa[arr] + (r0 + e) * es, lds + e * stride + t.off[arr], es);
+    }
+  }
+}
+
+template <bool ALIGNED>
+__global__ __launch_bounds__(256) void soa_to_aos_kernel(const XposeArgs* __restrict__ tp,
+                                                         int tile) {
+  extern __shared__ uint4 lds_u4[];
+  char* lds = reinterpret_cast<char*>(lds_u4);
+  const XposeArgs& t = *tp;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * tile;
+  const int nrec = static_cast<int>(min(static_cast<int64_t>(tile), t.n - r0));
+  const int stride = t.stride;
+  const int nbytes = nrec * stride;
+  // padding bytes are whatever no field writes: zero them first
+  for (int c = threadIdx.x; c < (nbytes + 15) >> 4; c += blockDim.x)
+    lds_u4[c] = make_uint4(0u, 0u, 0u, 0u);
+  __syncthreads();
+  if (nrec == tile) {
+    ChunkCursor c;
+    for (int w = threadIdx.x; seek_chunk(t, tile, w, c); w += blockDim.x) {
+      const int es = t.es[c.arr];
+      const int per = 16 / es;
+      const int e0 = (w - c.base) * per;
+      const uint4 val = *reinterpret_cast<const uint4*>(t.soa[c.arr] + (r0 + e0) * es);
+      const char* vb = reinterpret_cast<const char*>(&val);
+      char* dst = lds + e0 * stride + t.off[c.arr];
+      for (int q = 0; q < per; ++q) copy_elem<ALIGNED>(dst + q * stride, vb + q * es, es);
+    }
+  } else {
+    for (int w = threadIdx.x; w < nrec * t.narrays; w += blockDim.x) {
+      const int arr = w / nrec, e = w - arr * nrec;
+      const int es = t.es[arr];
+      copy_elem<ALIGNED>(lds + e * stride + t.off[arr], t.soa[arr] + (r0 + e) * es, es);
+    }
+  }
+  __syncthreads();
+  stage_out(t.aos + r0 * stride, lds, nbytes);
+}
+
+// ------------------------------------------------------------------- fill
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+// SplitMix64 output function (Steele, Lea & Flood 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// i-th output of a SplitMix64 generator seeded with the s-th output of one
+// seeded with `seed`.
+__device__ __forceinline__ uint64_t draw(uint64_t seed, uint64_t s, uint64_t i) {
+  return mix64(mix64(seed + kGamma * (s + 1)) + kGamma * (i + 1));
+}
+
+__device__ __forceinline__ double unit_co(uint64_t r) {  // [0, 1)
+  return static_cast<double>(r >> 11) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ double unit_oc(uint64_t r) {  // (0, 1]
+  return static_cast<double>((r >> 11) + 1) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ void store_value(void* arr, int64_t i, int dtype, double f, uint64_t bits,
+                                            bool is_real) {
+  switch (dtype) {
+    case kF64: static_cast<double*>(arr)[i] = is_real ? f : static_cast<double>(bits); break;
+    case kF32: static_cast<float*>(arr)[i] = static_cast<float>(is_real ? f : static_cast<double>(bits)); break;
+    case kI64: static_cast<uint64_t*>(arr)[i] = bits; break;
+    case kI32: static_cast<uint32_t*>(arr)[i] = static_cast<uint32_t>(bits); break;
+    default: static_cast<uint8_t*>(arr)[i] = static_cast<uint8_t>(bits); break;
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(FillArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const uint64_t r = draw(a.seed, a.stream, static_cast<uint64_t>(i));
+  switch (a.rule) {
+    case kFillIndex: store_value(a.arr, i, a.dtype, 0.0, static_cast<uint64_t>(i), false); break;
+    case kFillRaw: store_value(a.arr, i, a.dtype, 0.0, r, false); break;
+    case kFillTop8: store_value(a.arr, i, a.dtype, 0.0, r >> 56, false); break;
+    case kFillBox: store_value(a.arr, i, a.dtype, kBoxL * unit_co(r), 0, true); break;
+    case kFillMass: store_value(a.arr, i, a.dtype, 0.5 + 1.5 * unit_co(r), 0, true); break;
+    case kFillUnit: store_value(a.arr, i, a.dtype, unit_co(r), 0, true); break;
+    default: {  // Box-Muller
+      const double u1 = unit_oc(r);
+      const double u2 = unit_co(draw(a.seed, a.stream + 1, static_cast<uint64_t>(i)));
+      store_value(a.arr, i, a.dtype, sqrt(-2.0 * log(u1)) * cos(kBoxL * u2), 0, true);
+      break;
+    }
+  }
+}
+
+template <typename PT, typename VT>
+__global__ __launch_bounds__(256) void vel_from_field_kernel(SoaStepArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const PT* px = static_cast<const PT*>(a.pos[0]);
+  const PT* py = static_cast<const PT*>(a.pos[1]);
+  const PT* pz = static_cast<const PT*>(a.pos[2]);
+  double u0, u1, u2;
+  abc_field(to_abc(a.abc), widen(px[i]), widen(py[i]), widen(pz[i]), u0, u1, u2);
+  static_cast<VT*>(a.vel[0])[i] = static_cast<VT>(u0);
+  static_cast<VT*>(a.vel[1])[i] = static_cast<VT>(u1);
+  static_cast<VT*>(a.vel[2])[i] = static_cast<VT>(u2);
+}
+
+// ------------------------------------------------------------------- copy
+
+__global__ __launch_bounds__(256) void copy16_kernel(uint4* __restrict__ dst,
+                                                     const uint4* __restrict__ src, int64_t n16) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n16;
+       i += stride)
+    dst[i] = src[i];
+}
+
+__global__ void copy_tail_kernel(char* dst, const char* src, int64_t from, int64_t bytes) {
+  const int64_t i = from + threadIdx.x;
+  if (i < bytes) dst[i] = src[i];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_soa_step(int integ, int pos_t, int vel_t, int vec, int block,
+                           const SoaStepArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const bool pd = pos_t == kF64, vd = vel_t == kF64;
+  switch (integ) {
+    case kEuler:
+      if (pd && !vd) return soa_step_vec<kEuler, double, float>(vec, block, a, s);
+      if (pd && vd) return soa_step_vec<kEuler, double, double>(vec, block, a, s);
+      if (!pd && !vd) return soa_step_vec<kEuler, float, float>(vec, block, a, s);
+      return soa_step_vec<kEuler, float, double>(vec, block, a, s);
+    case kEulerAcc:
+      if (pd && !vd) return soa_step_vec<kEulerAcc, double, float>(vec, block, a, s);
+      if (pd && vd) return soa_step_vec<kEulerAcc, double, double>(vec, block, a, s);
+      if (!pd && !vd) return soa_step_vec<kEulerAcc, float, float>(vec, block, a, s);
+      return soa_step_vec<kEulerAcc, float, double>(vec, block, a, s);
+    case kRk2Abc:
+      if (!pd) return hipErrorInvalidValue;
+      if (vd) return soa_step_vec<kRk2Abc, double, double>(vec, block, a, s);
+      return soa_step_vec<kRk2Abc, double, float>(vec, block, a, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+int aos_tile_records(int stride, int block) {
+  int tile = block;
+  const int cap = (kLdsBudget / stride) & ~15;
+  if (tile > cap) tile = cap;
+  if (tile < 16) tile = 16;
+  return tile;
+}
+
+static hipError_t aos_any(int integ, int pos_t, int vel_t, bool aligned, bool naive, int block,
+                          const AosStepArgs& a, hipStream_t s) {
+  switch (integ) {
+    case kEuler: return aos_dispatch<kEuler>(pos_t, vel_t, aligned, naive, block, a, s);
+    case kEulerAcc: return aos_dispatch<kEulerAcc>(pos_t, vel_t, aligned, naive, block, a, s);
+    case kRk2Abc: return aos_dispatch<kRk2Abc>(pos_t, vel_t, aligned, naive, block, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_aos_step(int integ, int pos_t, int vel_t, bool aligned, int block,
+                           const AosStepArgs& a, hipStream_t s) {
+  return aos_any(integ, pos_t, vel_t, aligned, false, block, a, s);
+}
+
+hipError_t launch_aos_naive(int integ, int pos_t, int vel_t, bool aligned, int block,
+                            const AosStepArgs& a, hipStream_t s) {
+  return aos_any(integ, pos_t, vel_t, aligned, true, block, a, s);
+}
+
+static int xpose_tile(int stride) {
+  // 256 records per tile unless the staging would exceed the LDS budget;
+  // always a multiple of 16 so every tile starts on a 16-byte boundary.
+  return aos_tile_records(stride, 256);
+}
+
+hipError_t launch_xpose(bool to_soa, const XposeArgs& host, const XposeArgs* dev,
+                            hipStream_t s) {
+  if (host.n == 0) return hipSuccess;
+  const int tile = xpose_tile(host.stride);
+  const int64_t grid = (host.n + tile - 1) / tile;
+  const size_t lds = (static_cast<size_t>(tile) * host.stride + 15) & ~static_cast<size_t>(15);
+  if (to_soa) {
+    if (host.aligned)
+      hipLaunchKernelGGL((aos_to_soa_kernel<true>), dim3(grid), dim3(256), lds, s, dev, tile);
+    else
+      hipLaunchKernelGGL((aos_to_soa_kernel<false>), dim3(grid), dim3(256), lds, s, dev, tile);
+  } else {
+    if (host.aligned)
+      hipLaunchKernelGGL((soa_to_aos_kernel<true>), dim3(grid), dim3(256), lds, s, dev, tile);
+    else
+      hipLaunchKernelGGL((soa_to_aos_kernel<false>), dim3(grid), dim3(256), lds, s, dev, tile);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(const FillArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const int64_t grid = (a.n + 255) / 256;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_vel_from_field(int pos_t, int vel_t, const SoaStepArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const int64_t grid = (a.n + 255) / 256;
+  if (pos_t == kF64 && vel_t == kF32)
+    hipLaunchKernelGGL((vel_from_field_kernel<double, float>), dim3(grid), dim3(256), 0, s, a);
+  else if (pos_t == kF64 && vel_t == kF64)
+    hipLaunchKernelGGL((vel_from_field_kernel<double, double>), dim3(grid), dim3(256), 0, s, a);
+  else if (pos_t == kF32 && vel_t == kF32)
+    hipLaunchKernelGGL((vel_from_field_kernel<float, float>), dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((vel_from_field_kernel<float, double>), dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy16(void* dst, const void* src, int64_t bytes, hipStream_t s) {
+  const int64_t n16 = bytes >> 4;
+  if (n16 > 0) {
+    int64_t grid = (n16 + 255) / 256;
+    if (grid > 256 * 32) grid = 256 * 32;  // grid-stride: 32 workgroups per CU
+    hipLaunchKernelGGL(copy16_kernel, dim3(grid), dim3(256), 0, s, static_cast<uint4*>(dst),
+                       static_cast<const uint4*>(src), n16);
+  }
+  if (bytes & 15) {
+    hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(16), 0, s, static_cast<char*>(dst),
+                       static_cast<const char*>(src), n16 << 4, bytes);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace soax

@@ -1,0 +1,180 @@
+// launch.h -- interface between the host side of the C ABI (soax_host.cpp)
+// and the kernel translation units.  Launchers validate nothing: the host
+// side has already checked sizes, types and alignment.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace soax {
+
+struct Abc;
+
+constexpr int kMaxFields = 32;
+constexpr int kMaxArrays = 3 * kMaxFields;
+
+// Element type codes (same values as soax_dtype).
+enum Dtype : int32_t { kI8 = 1, kU8 = 2, kI32 = 3, kI64 = 4, kF32 = 5, kF64 = 6 };
+enum Integrator : int32_t { kEuler = 0, kEulerAcc = 1, kRk2Abc = 2 };
+
+inline int dtype_size(int32_t t) {
+  switch (t) {
+    case kI8: case kU8: return 1;
+    case kI32: case kF32: return 4;
+    case kI64: case kF64: return 8;
+    default: return 0;
+  }
+}
+
+struct AbcParams {
+  double A, B, C;
+};
+
+// ------------------------------------------------------------------ steps
+
+struct SoaStepArgs {
+  void* pos[3];
+  void* vel[3];
+  const void* acc[3];  // Euler-with-acceleration only; same type as vel
+  int64_t n;
+  double dt;
+  AbcParams abc;
+  int32_t wrap;
+};
+
+// vec = particles per thread (1, 2, 4; 2 and 4 need 16-byte aligned arrays).
+hipError_t launch_soa_step(int integ, int pos_t, int vel_t, int vec, int block,
+                           const SoaStepArgs& a, hipStream_t s);
+
+struct AosStepArgs {
+  char* aos;
+  int64_t n;
+  int32_t stride;
+  int32_t off_pos, off_vel, off_acc;
+  double dt;
+  AbcParams abc;
+  int32_t wrap;
+};
+
+// LDS-staged tile kernel: needs a 16-byte aligned buffer; `aligned` says
+// every pos/vel/acc element is naturally aligned inside a record.
+hipError_t launch_aos_step(int integ, int pos_t, int vel_t, bool aligned, int block,
+                           const AosStepArgs& a, hipStream_t s);
+// One thread per record, direct per-field global accesses.
+hipError_t launch_aos_naive(int integ, int pos_t, int vel_t, bool aligned, int block,
+                            const AosStepArgs& a, hipStream_t s);
+// Largest tile (records) whose LDS staging fits the per-block budget.
+int aos_tile_records(int stride, int block);
+
+// -------------------------------------------------------------- transposes
+
+struct XposeArgs {
+  char* aos;
+  int64_t n;
+  int32_t stride;
+  int32_t narrays;
+  int32_t aligned;  // every element naturally aligned inside the record
+  char* soa[kMaxArrays];
+  int32_t off[kMaxArrays];  // byte offset of the element inside the record
+  int32_t es[kMaxArrays];   // element size
+};
+
+// `host` is a host copy of the table the kernels read from `dev` (device
+// memory, uploaded once per set).
+hipError_t launch_xpose(bool to_soa, const XposeArgs& host, const XposeArgs* dev, hipStream_t s);
+
+// -------------------------------------------------------------------- fill
+
+enum FillRule : int32_t {
+  kFillIndex = 0,     // i
+  kFillRaw = 1,       // low bytes of the draw
+  kFillTop8 = 2,      // draw >> 56
+  kFillBox = 3,       // L * U[0,1)
+  kFillNormal = 4,    // Box-Muller N(0,1) from streams s and s+1
+  kFillMass = 5,      // 0.5 + 1.5 * U[0,1)
+  kFillUnit = 6,      // U[0,1)
+};
+
+struct FillArgs {
+  void* arr;
+  int64_t n;
+  uint64_t seed;
+  uint64_t stream;
+  int32_t dtype;
+  int32_t rule;
+};
+
+hipError_t launch_fill(const FillArgs& a, hipStream_t s);
+// vel = u(pos) (vel_mode 1 of the fill).
+hipError_t launch_vel_from_field(int pos_t, int vel_t, const SoaStepArgs& a, hipStream_t s);
+
+// --------------------------------------------------------------- utilities
+
+hipError_t launch_copy16(void* dst, const void* src, int64_t bytes, hipStream_t s);
+
+// --------------------------------------------------------------- adjoint
+
+struct CkptArgs {
+  const double* x0[3];
+  double* xT[3];
+  double* tape;
+  int64_t n;
+  int64_t nsteps;
+  int64_t k;
+  double dt;
+  AbcParams abc;
+};
+hipError_t launch_rk2_forward_ckpt(const CkptArgs& a, hipStream_t s);
+
+struct AdjointArgs {
+  const double* tape;
+  const double* lam[3];
+  double* gx[3];
+  double* partial;  // [nblocks][3] per-block parameter-gradient sums
+  double* grad_abc;
+  int64_t n;
+  int64_t nsteps;
+  int64_t k;
+  double dt;
+  AbcParams abc;
+};
+// number of per-block partial sums launch_adjoint needs (3 doubles each)
+int64_t adjoint_partials(int64_t n);
+hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s);
+
+struct LossArgs {
+  const double* xT[3];
+  const double* target[3];
+  double* lam[3];
+  double* partial;
+  double* loss;
+  int64_t n;
+};
+int64_t loss_partials(int64_t n);
+hipError_t launch_sqdist_loss(const LossArgs& a, hipStream_t s);
+
+// -------------------------------------------------------------- batching
+
+struct BatchSet {
+  double* pos[3];
+  void* vel[3];
+  int64_t n;
+  int64_t tile_begin;  // first tile of this set in the batch's tile list
+  double dt;
+  double A, B, C;
+};
+
+struct BatchLaunch {
+  const BatchSet* sets;   // device table
+  const int32_t* tile_set;  // device: set index of every tile
+  int64_t ntiles;
+  int32_t nsets;
+  int32_t tile;       // particles per tile = block * per_thread
+  int32_t block;
+  int32_t per_thread;
+  int32_t grid;
+  int32_t vel_t;
+};
+hipError_t launch_batch_rk2(const BatchLaunch& b, hipStream_t s);
+
+}  // namespace soax

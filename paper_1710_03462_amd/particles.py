@@ -1,0 +1,154 @@
+"""Particle sets backed by torch device memory.
+
+A ParticleSet owns one torch tensor per (property, component) -- the SoA
+copy -- and one uint8 tensor of records -- the AoS copy -- and binds them to
+the library with soax_bind.  Every operation runs in the library's kernels
+on the current torch stream; this module only marshals arguments.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+TORCH_DTYPE = {"i8": torch.int8, "u8": torch.uint8, "i32": torch.int32, "i64": torch.int64,
+               "f32": torch.float32, "f64": torch.float64}
+NUMPY_DTYPE = {"i8": np.int8, "u8": np.uint8, "i32": np.int32, "i64": np.int64,
+               "f32": np.float32, "f64": np.float64}
+
+
+def current_stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def params(abc=None, wrap=False):
+    a = (0.0, 0.0, 0.0) if abc is None else tuple(float(v) for v in abc)
+    return _lib.Params(a[0], a[1], a[2], int(bool(wrap)))
+
+
+class Schema:
+    """An ordered list of (name, dtype, dim[, tag]) properties."""
+
+    def __init__(self, fields, packed=False):
+        self.fields = [tuple(f) for f in fields]
+        self.packed = bool(packed)
+        self._c, self._keep = _lib.make_schema(self.fields, self.packed)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self._c)
+
+    def layout(self):
+        """(AoS field offsets, AoS record stride, SoA bytes per particle)."""
+        off = (ctypes.c_int64 * len(self.fields))()
+        stride, soa = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().soax_schema_layout(self.ref, off, ctypes.byref(stride), ctypes.byref(soa)),
+              "soax_schema_layout")
+        return list(off), stride.value, soa.value
+
+    def arrays(self):
+        return [(f[0], c, f[1]) for f in self.fields for c in range(int(f[2]))]
+
+    def array_index(self, name, comp=0):
+        a = 0
+        for f in self.fields:
+            if f[0] == name:
+                return a + comp
+            a += int(f[2])
+        raise KeyError(name)
+
+
+class ParticleSet:
+    """n particles of a schema, both layouts resident on the current GPU."""
+
+    def __init__(self, fields, n, packed=False, soa=True, aos=True, pad=64):
+        if not torch.cuda.is_available():
+            raise RuntimeError("ParticleSet needs a GPU")
+        self.schema = Schema(fields, packed)
+        self.n = int(n)
+        self.offsets, self.stride, self.soa_bytes = self.schema.layout()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        ld = max(pad, -(-self.n // pad) * pad)
+        self.soa = None
+        if soa:
+            self._soa_store = [torch.empty(ld, dtype=TORCH_DTYPE[t], device=dev)
+                               for _, _, t in self.schema.arrays()]
+            self.soa = [b[: self.n] for b in self._soa_store]
+        self.aos = torch.zeros(max(self.n * self.stride, 16), dtype=torch.uint8,
+                               device=dev) if aos else None
+        ptrs = None
+        if soa:
+            ptrs = (ctypes.c_void_p * len(self.soa))(*[t.data_ptr() for t in self.soa])
+        h = ctypes.c_void_p()
+        check(lib().soax_bind(self.schema.ref, self.n, ptrs,
+                              ctypes.c_void_p(self.aos.data_ptr()) if aos else None,
+                              ctypes.byref(h)), "soax_bind")
+        self.handle = h
+
+    # -------------------------------------------------------------- lifetime
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().soax_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ operations
+    def fill(self, seed=0, vel_mode=0, abc=None):
+        p = params(abc)
+        check(lib().soax_fill(self.handle, seed, vel_mode, ctypes.byref(p), current_stream()),
+              "soax_fill")
+
+    def step(self, layout, integrator, dt, nsteps, abc=None, wrap=True):
+        lay = _lib.LAYOUTS[layout] if isinstance(layout, str) else layout
+        integ = _lib.INTEGRATORS[integrator] if isinstance(integrator, str) else integrator
+        p = params(abc, wrap)
+        check(lib().soax_step(self.handle, lay, integ, float(dt), int(nsteps), ctypes.byref(p),
+                              current_stream()), "soax_step")
+
+    def step_config(self, layout, block=0, per_thread=0):
+        lay = _lib.LAYOUTS[layout] if isinstance(layout, str) else layout
+        check(lib().soax_step_config(self.handle, lay, block, per_thread), "soax_step_config")
+
+    def aos_to_soa(self):
+        check(lib().soax_aos_to_soa(self.handle, current_stream()), "soax_aos_to_soa")
+
+    def soa_to_aos(self):
+        check(lib().soax_soa_to_aos(self.handle, current_stream()), "soax_soa_to_aos")
+
+    def get_record(self, layout, i):
+        buf = (ctypes.c_uint8 * self.stride)()
+        lay = _lib.LAYOUTS[layout] if isinstance(layout, str) else layout
+        check(lib().soax_get_record(self.handle, lay, int(i), buf), "soax_get_record")
+        return bytes(buf)
+
+    # --------------------------------------------------------- host transfer
+    def array(self, name, comp=0):
+        return self.soa[self.schema.array_index(name, comp)]
+
+    def upload_soa(self, arrays):
+        for dst, src in zip(self.soa, arrays):
+            dst.copy_(torch.from_numpy(np.ascontiguousarray(src)))
+
+    def download_soa(self):
+        return [t.cpu().numpy() for t in self.soa]
+
+    def upload_aos(self, buf):
+        self.aos[: self.n * self.stride].copy_(torch.from_numpy(np.ascontiguousarray(buf)))
+
+    def download_aos(self):
+        return self.aos[: self.n * self.stride].cpu().numpy()
+
+
+def copy(dst, src):
+    """dst <- src (16-byte aligned tensors of equal byte size) with the copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() >= nbytes
+    check(lib().soax_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                          nbytes, current_stream()), "soax_copy")

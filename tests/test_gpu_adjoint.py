@@ -1,0 +1,118 @@
+"""GPU parity of the checkpointed RK2 forward, the discrete adjoint and the
+loss against the CPU oracle (which stores every state), plus properties the
+checkpointing must keep: gradients bit-identical for every k, and a torch
+autograd round trip."""
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+from gpu_util import L
+
+pytestmark = pytest.mark.gpu
+
+soax = pytest.importorskip("paper_1710_03462_amd")
+
+ABC = [1.0, 0.8, 0.6]
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_fwd_bwd(x0, target, abc, dt, nsteps, k):
+    abc_host = soax.autograd._host3(torch.tensor(abc, dtype=torch.float64))
+    xT, tape = soax.forward_ckpt(gpu(x0), abc_host, dt, nsteps, k)
+    loss, lam = soax.sqdist_loss(xT, gpu(target))
+    gx, gabc = soax.adjoint(tape, lam, abc_host, dt, nsteps, k)
+    torch.cuda.synchronize()
+    return (xT.cpu().numpy(), tape.cpu().numpy(), float(loss.item()), gx.cpu().numpy(),
+            gabc.cpu().numpy())
+
+
+def ref_fwd_bwd(ref, x0, target, abc, dt, nsteps):
+    xT, states = ref.rk2_forward(x0, abc, dt, nsteps, store_states=True)
+    loss, lam = ref.sqdist_loss(xT, target)
+    gx, gabc = ref.adjoint(x0, lam, abc, dt, nsteps)
+    return xT, states, loss, gx, gabc
+
+
+def check_grads(gx, gabc, rgx, rgabc):
+    assert np.abs(gx - rgx).max() <= 1e-6 * np.abs(rgx).max()
+    assert np.all(np.abs(gabc - rgabc) <= 1e-6 * np.abs(rgabc))
+
+
+@pytest.mark.parametrize("n,nsteps,k", [(1, 200, 20), (2000, 200, 20), (777, 203, 20),
+                                        (300, 50, 7), (257, 10, 64), (129, 40, 1)])
+def test_forward_adjoint_match_oracle(ref, n, nsteps, k):
+    dt = 5e-3
+    x0, target = si.adjoint_inputs(n, seed=n + nsteps)
+    xT, tape, loss, gx, gabc = gpu_fwd_bwd(x0, target, ABC, dt, nsteps, k)
+    rxT, states, rloss, rgx, rgabc = ref_fwd_bwd(ref, x0, target, ABC, dt, nsteps)
+    assert np.abs(xT - rxT).max() <= 1e-12 * L
+    for c in range(-(-nsteps // k)):
+        assert np.abs(tape[c] - states[c * k]).max() <= 1e-12 * L
+    assert abs(loss - rloss) <= 1e-12 * abs(rloss)
+    check_grads(gx, gabc, rgx, rgabc)
+
+
+def test_gradients_bit_identical_for_every_k():
+    n, nsteps, dt = 1500, 200, 5e-3
+    x0, target = si.adjoint_inputs(n, seed=5)
+    base = gpu_fwd_bwd(x0, target, ABC, dt, nsteps, 20)
+    for k in (1, 7, 32, 33, 200, 1000):
+        got = gpu_fwd_bwd(x0, target, ABC, dt, nsteps, k)
+        assert np.array_equal(got[0], base[0]), k
+        assert np.array_equal(got[3], base[3]), k
+        assert np.array_equal(got[4], base[4]), k
+
+
+def test_zero_steps_and_empty():
+    x0, target = si.adjoint_inputs(10, seed=1)
+    xT, tape, loss, gx, gabc = gpu_fwd_bwd(x0, target, ABC, 5e-3, 0, 20)
+    assert np.array_equal(xT, x0)
+    assert np.array_equal(gx, 2 * (x0 - target))
+    assert not gabc.any()
+    e = np.zeros((3, 0))
+    xT, tape, loss, gx, gabc = gpu_fwd_bwd(e, e, ABC, 5e-3, 10, 3)
+    assert loss == 0.0 and not gabc.any()
+
+
+def test_single_amplitude_closed_form_on_gpu():
+    n, nsteps, dt, A = 1000, 40, 5e-3, 1.1
+    T = nsteps * dt
+    x0, target = si.adjoint_inputs(n, seed=2)
+    xT, _, _, gx, gabc = gpu_fwd_bwd(x0, target, [A, 0.0, 0.0], dt, nsteps, 20)
+    X, Y, Z = x0
+    ex, ey, ez = xT - target
+    dA = (2 * ex * T * np.sin(Z) + 2 * ey * T * np.cos(Z)).sum()
+    assert abs(gabc[0] - dA) <= 1e-9 * abs(dA)
+    dz = 2 * ex * T * A * np.cos(Z) - 2 * ey * T * A * np.sin(Z) + 2 * ez
+    assert np.abs(gx[2] - dz).max() <= 1e-9 * np.abs(dz).max()
+
+
+def test_autograd_function_matches_oracle(ref):
+    n, nsteps, dt, k = 999, 120, 5e-3, 20
+    x0, target = si.adjoint_inputs(n, seed=3)
+    pos0 = gpu(x0).requires_grad_(True)
+    abc = torch.tensor(ABC, dtype=torch.float64, device="cuda", requires_grad=True)
+    xT = soax.rk2_advect(pos0, abc, dt, nsteps, k)
+    loss = ((xT - gpu(target)) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    _, _, rloss, rgx, rgabc = ref_fwd_bwd(ref, x0, target, ABC, dt, nsteps)
+    assert abs(loss.item() - rloss) <= 1e-12 * rloss
+    check_grads(pos0.grad.cpu().numpy(), abc.grad.cpu().numpy(), rgx, rgabc)
+
+
+def test_parameter_gradient_matches_gpu_finite_differences():
+    n, nsteps, dt, k, h = 4000, 200, 5e-3, 20, 1e-6
+    x0, target = si.adjoint_inputs(n, seed=4)
+    _, _, _, _, gabc = gpu_fwd_bwd(x0, target, ABC, dt, nsteps, k)
+    for j in range(3):
+        p, m = list(ABC), list(ABC)
+        p[j] += h
+        m[j] -= h
+        fd = (gpu_fwd_bwd(x0, target, p, dt, nsteps, k)[2] -
+              gpu_fwd_bwd(x0, target, m, dt, nsteps, k)[2]) / (2 * h)
+        assert abs(fd - gabc[j]) <= 1e-6 * abs(gabc[j])

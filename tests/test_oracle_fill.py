@@ -102,3 +102,14 @@ def test_fill_velocity_from_field(ref):
         u = ref.field(abc, x)
         for d in range(3):
             assert arrs[sch.array_index("vel", d)][i] == np.float32(u[d])
+
+
+def test_fill_range_matches_full_fill(ref):
+    sch = ref.Schema(WIDE_FIELDS)
+    full = ref.fill(sch, 5000, seed=9, vel_mode=0)
+    part = ref.fill_range(sch, 1234, 777, seed=9)
+    assert all(np.array_equal(a[1234:1234 + 777], b) for a, b in zip(full, part))
+    sch = ref.Schema(BASE_FIELDS)
+    full = ref.fill(sch, 3000, seed=2, vel_mode=1, abc=[1, 1, 1])
+    part = ref.fill_range(sch, 2990, 10, seed=2, vel_mode=1, abc=[1, 1, 1])
+    assert all(np.array_equal(a[2990:], b) for a, b in zip(full, part))
