@@ -1,0 +1,337 @@
+"""Benchmark of the SoA/AoS particle-update hot path on one MI355X.
+
+Timed step (the headline `value`): one pass of 50 RK2 steps in the ABC field
+(A = B = C = 1, dt = 1e-3, periodic wrap) over 1e8 particles of the record
+{int32 id; fp64 pos[3]; fp32 vel[3]} stored as SoA, inputs already resident
+in HBM.  value = particle-updates/s = 1e8 * 50 * K / elapsed.
+
+Every other row of the hot path is timed separately on the same GPU and
+reported under "rows": the same RK2 workload in the LDS-staged and naive AoS
+layouts, the Euler step at 1e8 particles in all layouts (the HBM headline),
+the wide-record transposes and Euler-with-acceleration steps (3e7),
+checkpointed RK2 forward and forward + adjoint (1e7, 200 steps, k = 20),
+and 256 uneven sets stepped 100 times by one graph of persistent launches
+versus one launch per set (tuned shape).  "copy" is the 16-byte copy
+kernel's bandwidth on 4 GiB, the achievable HBM ceiling.
+
+Prints ONE JSON line on stdout (progress goes to stderr).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("particle-updates/s + achieved HBM GB/s (SoA vs AoS, fwd and fwd+adjoint), 1 GPU")
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1710_03462_amd", "csrc", f)
+                  for f in ("k_step.hip", "device_math.h")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sources_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+class Timer:
+    """HIP events on torch's current stream, which every library call uses."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.a.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record()
+        self.torch.cuda.synchronize()
+        self.ms = self.a.elapsed_time(self.b)
+
+
+def rate(count, ms):
+    return count / (ms * 1e-3) if ms > 0 else float("nan")
+
+
+def gbs(nbytes, ms):
+    return nbytes / (ms * 1e-3) / 1e9 if ms > 0 else float("nan")
+
+
+# ------------------------------------------------------------------- rows
+
+def bench_rk2(torch, soax, ps, n, nsteps, layout, reps):
+    ps.step(layout, "rk2_abc", 1e-3, nsteps, abc=[1, 1, 1], wrap=True)  # warm-up pass
+    with Timer(torch) as t:
+        for _ in range(reps):
+            ps.step(layout, "rk2_abc", 1e-3, nsteps, abc=[1, 1, 1], wrap=True)
+    per_launch = t.ms / (reps * nsteps)
+    ups = rate(n * nsteps * reps, t.ms)
+    phys = 60 if layout == "soa" else 2 * ps.stride
+    return {"updates_per_s": ups, "ms_per_launch": per_launch,
+            "alg_GBps": gbs(60 * n, per_launch), "physical_GBps": gbs(phys * n, per_launch),
+            "steps": nsteps * reps}
+
+
+def bench_euler(torch, soax, ps, n, nsteps, layout):
+    ps.step(layout, "euler", 1e-3, 2, wrap=True)
+    with Timer(torch) as t:
+        ps.step(layout, "euler", 1e-3, nsteps, wrap=True)
+    per_launch = t.ms / nsteps
+    phys = 60 if layout == "soa" else 2 * ps.stride
+    return {"updates_per_s": rate(n * nsteps, t.ms), "ms_per_launch": per_launch,
+            "alg_GBps": gbs(60 * n, per_launch), "physical_GBps": gbs(phys * n, per_launch),
+            "frac_of_peak": gbs(phys * n, per_launch) / HBM_PEAK_GBS, "steps": nsteps}
+
+
+def bench_copy(torch, soax, nbytes=4 << 30):
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    soax.copy(dst, src)
+    reps = 10
+    with Timer(torch) as t:
+        for _ in range(reps):
+            soax.copy(dst, src)
+    per = t.ms / reps
+    out = {"bytes": nbytes, "ms_per_launch": per, "GBps": gbs(2 * nbytes, per),
+           "frac_of_peak": gbs(2 * nbytes, per) / HBM_PEAK_GBS}
+    del src, dst
+    return out
+
+
+def bench_wide(torch, soax, si, n):
+    ps = soax.ParticleSet(si.WIDE_FIELDS, n)
+    ps.fill(seed=0)
+    ps.soa_to_aos()
+    ps.aos_to_soa()
+    ps.step("soa", "euler_acc", 1e-3, 2, wrap=True)
+    alg_x = 2 * ps.soa_bytes
+    phys_x = ps.soa_bytes + ps.stride
+    with Timer(torch) as t1:
+        ps.aos_to_soa()
+    with Timer(torch) as t2:
+        ps.step("soa", "euler_acc", 1e-3, 20, wrap=True)
+    with Timer(torch) as t3:
+        ps.soa_to_aos()
+    res = {"n": n, "aos_to_soa": {"ms": t1.ms, "alg_GBps": gbs(alg_x * n, t1.ms),
+                                  "physical_GBps": gbs(phys_x * n, t1.ms)},
+           "euler_acc_soa": {"updates_per_s": rate(n * 20, t2.ms), "ms_per_launch": t2.ms / 20,
+                             "alg_GBps": gbs(84 * n, t2.ms / 20)},
+           "soa_to_aos": {"ms": t3.ms, "alg_GBps": gbs(alg_x * n, t3.ms),
+                          "physical_GBps": gbs(phys_x * n, t3.ms)}}
+    ps.close()
+    return res
+
+
+def bench_adjoint(torch, soax, si, n, nsteps=200, k=20):
+    src = soax.ParticleSet(si.BASE_FIELDS, n, aos=False)
+    src.fill(seed=0)
+    x0 = torch.stack([src.array("pos", d) for d in range(3)]).contiguous()
+    src.fill(seed=1)
+    target = torch.stack([src.array("pos", d) for d in range(3)]).contiguous()
+    src.close()
+    abc = soax.autograd._host3(torch.tensor([1.0, 0.8, 0.6], dtype=torch.float64))
+    dt = 5e-3
+    soax.forward_ckpt(x0, abc, dt, nsteps, k)
+    with Timer(torch) as tf:
+        xT, tape = soax.forward_ckpt(x0, abc, dt, nsteps, k)
+    with Timer(torch) as tb:
+        xT, tape = soax.forward_ckpt(x0, abc, dt, nsteps, k)
+        loss, lam = soax.sqdist_loss(xT, target)
+        gx, gabc = soax.adjoint(tape, lam, abc, dt, nsteps, k)
+    res = {"n": n, "nsteps": nsteps, "k": k,
+           "fwd": {"ms": tf.ms, "particle_steps_per_s": rate(n * nsteps, tf.ms)},
+           "fwd_adjoint": {"ms": tb.ms, "particle_steps_per_s": rate(n * nsteps, tb.ms)},
+           "loss": float(loss.item())}
+    del x0, target, xT, tape, lam, gx
+    return res
+
+
+def bench_batch(torch, soax, si, nsets=256, nsteps=100):
+    sizes, dts, abc = si.batch_plan(nsets, seed=0)
+    sets = []
+    for s, n in enumerate(sizes):
+        ps = soax.ParticleSet(si.BASE_FIELDS, int(n), aos=False)
+        ps.fill(seed=s, vel_mode=1, abc=abc[s])
+        sets.append(ps)
+    total = int(sizes.sum())
+    b = soax.Batch(sets)
+    t0 = time.perf_counter()
+    cfg = b.tune()
+    tune_s = time.perf_counter() - t0
+    b.step(dts, abc, nsteps, mode=soax.GRAPH)  # capture + warm-up
+    with Timer(torch) as tg:
+        b.step(dts, abc, nsteps, mode=soax.GRAPH)
+    with Timer(torch) as tp:
+        b.step(dts, abc, nsteps, mode=soax.PERSISTENT)
+    b.step(dts, abc, 2, mode=soax.PER_SET)
+    with Timer(torch) as ts:
+        b.step(dts, abc, nsteps, mode=soax.PER_SET)
+    res = {"nsets": nsets, "particles": total, "nsteps": nsteps,
+           "tuned": {"block": cfg[0], "per_thread": cfg[1], "blocks_per_cu": cfg[2],
+                     "tune_s": tune_s},
+           "graph": {"ms": tg.ms, "updates_per_s": rate(total * nsteps, tg.ms),
+                     "alg_GBps": gbs(60 * total * nsteps, tg.ms)},
+           "persistent_eager": {"ms": tp.ms, "updates_per_s": rate(total * nsteps, tp.ms)},
+           "per_set_launches": {"ms": ts.ms, "updates_per_s": rate(total * nsteps, ts.ms),
+                                "launches": nsets * nsteps},
+           "graph_speedup_vs_per_set": ts.ms / tg.ms}
+    b.close()
+    for ps in sets:
+        ps.close()
+    return res
+
+
+def cpu_baseline(ref, si, target_s=10.0):
+    """The oracle's RK2 SoA step on a bounded sample of the headline workload."""
+    sch = ref.Schema(si.BASE_FIELDS)
+    cores = ref.threads()
+    probe_n, probe_steps = 20000, 5
+    arrays = ref.fill(sch, probe_n, seed=0, vel_mode=1, abc=[1, 1, 1])
+    t0 = time.perf_counter()
+    ref.step_soa(sch, arrays, ref.RK2_ABC, 1e-3, probe_steps, abc=[1, 1, 1], wrap=True)
+    probe = (time.perf_counter() - t0) / (probe_n * probe_steps)
+    n = int(min(1e8, max(1e4, target_s / probe / 50)))
+    arrays = ref.fill(sch, n, seed=0, vel_mode=1, abc=[1, 1, 1])
+    t0 = time.perf_counter()
+    ref.step_soa(sch, arrays, ref.RK2_ABC, 1e-3, 50, abc=[1, 1, 1], wrap=True)
+    el = time.perf_counter() - t0
+    return {"value": n * 50 / el, "unit": "particle-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} particles x 50 RK2 steps of the same record and field "
+                      f"(SoA, OpenMP static schedule), {el:.1f} s"}
+
+
+def traffic_from_profiles(kernel, launches_bytes_key):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None when
+    the kernel sources changed since the counters were taken."""
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if data.get("sources_sha256_16") != sources_hash():
+        return None
+    ent = data.get("kernels", {}).get(kernel)
+    return ent.get(launches_bytes_key) if ent else None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed 50-step passes")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=float, default=1e8, help="particles of the headline workload")
+    ap.add_argument("--rows", default="all",
+                    help="comma list of extra rows: aos,euler,copy,wide,adjoint,batch | all | none")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards by particle range with no communication; see DESIGN.md)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1710_03462_amd as soax
+    import synth_inputs as si
+
+    soax.lib()
+    torch.cuda.set_device(0)
+    rows = {"aos", "euler", "copy", "wide", "adjoint", "batch"} if args.rows == "all" else \
+        set() if args.rows == "none" else set(args.rows.split(","))
+    n = int(args.n)
+    nsteps = 50
+
+    log(f"[bench] headline: {n} particles, {nsteps} RK2 steps per pass, SoA")
+    ps = soax.ParticleSet(si.BASE_FIELDS, n)
+    ps.fill(seed=0, vel_mode=1, abc=[1, 1, 1])
+    ps.soa_to_aos()
+    for _ in range(args.warmup):
+        ps.step("soa", "rk2_abc", 1e-3, nsteps, abc=[1, 1, 1], wrap=True)
+    torch.cuda.synchronize()
+    with Timer(torch) as t:
+        for _ in range(args.steps):
+            ps.step("soa", "rk2_abc", 1e-3, nsteps, abc=[1, 1, 1], wrap=True)
+    value = rate(n * nsteps * args.steps, t.ms)
+    ms_per_step = t.ms / args.steps
+    per_launch = t.ms / (args.steps * nsteps)
+    log(f"[bench] SoA RK2: {value:.4e} updates/s, {per_launch:.3f} ms/launch")
+
+    kname = "soa_step_kernel<RK2_ABC,double,float,4>"
+    traffic = traffic_from_profiles(kname, "hbm_bytes_per_launch")
+    roofline = {"kernel": kname, "bound": "hbm", "achieved": gbs(60 * n, per_launch),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs(60 * n, per_launch) / HBM_PEAK_GBS,
+                "traffic": traffic, "alg_bytes_per_launch": 60 * n,
+                "ms_per_launch": per_launch}
+
+    out_rows = {}
+    if "aos" in rows:
+        log("[bench] RK2 AoS (LDS-staged) and naive AoS")
+        out_rows["rk2_aos"] = bench_rk2(torch, soax, ps, n, nsteps, "aos", 1)
+        out_rows["rk2_aos_naive"] = bench_rk2(torch, soax, ps, n, nsteps, "aos_naive", 1)
+        out_rows["rk2_soa_over_aos"] = value / out_rows["rk2_aos"]["updates_per_s"]
+        out_rows["rk2_soa_over_aos_naive"] = value / out_rows["rk2_aos_naive"]["updates_per_s"]
+    if "euler" in rows:
+        log("[bench] Euler at the headline size, every layout")
+        for lay in ("soa", "aos", "aos_naive"):
+            out_rows[f"euler_{lay}"] = bench_euler(torch, soax, ps, n, 20, lay)
+        out_rows["euler_soa_over_aos"] = (out_rows["euler_soa"]["updates_per_s"] /
+                                          out_rows["euler_aos"]["updates_per_s"])
+    ps.close()
+    del ps
+    torch.cuda.empty_cache()
+    if "copy" in rows:
+        log("[bench] copy ceiling")
+        out_rows["copy"] = bench_copy(torch, soax)
+    if "wide" in rows:
+        log("[bench] wide record: transposes and Euler with acceleration")
+        out_rows["wide"] = bench_wide(torch, soax, si, 30_000_000)
+    if "adjoint" in rows:
+        log("[bench] RK2 forward and forward + adjoint")
+        out_rows["adjoint"] = bench_adjoint(torch, soax, si, 10_000_000)
+    if "batch" in rows:
+        log("[bench] batched sets")
+        out_rows["batch"] = bench_batch(torch, soax, si)
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle as ref
+        log("[bench] oracle CPU baseline")
+        cpu = cpu_baseline(ref, si)
+
+    line = {"metric": METRIC, "value": value, "unit": "particle-updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic (seeded SplitMix64 fill on the GPU)",
+            "config": {"workload": f"{n:.0e} particles {{int32 id; fp64 pos[3]; fp32 vel[3]}}, "
+                                   f"{nsteps} RK2 steps per pass in the ABC field A=B=C=1, "
+                                   "dt=1e-3, periodic wrap, SoA layout",
+                       "n": n, "nsteps_per_pass": nsteps, "layout": "soa",
+                       "parallelism": "none (1 GPU)"},
+            "roofline": roofline, "cpu_baseline": cpu, "rows": out_rows,
+            "device": torch.cuda.get_device_name(0)}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
