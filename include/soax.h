@@ -223,8 +223,9 @@ void soax_batch_destroy(soax_batch* batch);
 soax_status soax_batch_step(soax_batch* batch, const double* dt, const double* abc, int64_t nsteps,
                             int32_t mode, void* stream);
 
-/* Set the persistent kernel's shape (block threads, particles per thread,
- * workgroups per CU); 0 keeps the current value. */
+/* Set the persistent kernel's shape: block threads (64..512, multiple of 64),
+ * particles per thread (1, 2 or 4) and workgroups per CU (1..64); 0 keeps the
+ * current value. */
 soax_status soax_batch_config(soax_batch* batch, int32_t block, int32_t per_thread,
                               int32_t blocks_per_cu);
 soax_status soax_batch_get_config(const soax_batch* batch, int32_t* block, int32_t* per_thread,

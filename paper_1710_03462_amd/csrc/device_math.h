@@ -3,7 +3,8 @@
 //
 // Every expression is written as separate IEEE operations; the library is
 // compiled with -ffp-contract=off so that x + dt*v is a multiply and an add,
-// never an FMA (eq. (1) of Section 2 evaluated as written).
+// never an FMA (eq. (1) of Section 2 evaluated as written).  Only the sine
+// and cosine evaluations (trig.h) use fused multiply-adds, explicitly.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,6 +12,7 @@
 #include <type_traits>
 
 #include "launch.h"
+#include "trig.h"
 
 namespace soax {
 
@@ -21,6 +23,8 @@ struct Abc {
   double A, B, C;
 };
 
+__device__ __forceinline__ Abc to_abc(const AbcParams& p) { return Abc{p.A, p.B, p.C}; }
+
 // Wrap one coordinate displaced by much less than a box edge into [0, L).
 // A negative coordinate whose sum with L rounds to L is stored as 0.
 __device__ __forceinline__ double wrap_box(double x) {
@@ -30,33 +34,68 @@ __device__ __forceinline__ double wrap_box(double x) {
   return (x >= kBoxL) ? hi : ((x < 0.0) ? lo : x);
 }
 
-// sin and cos of one fp64 argument (ROCm device math library).
-__device__ __forceinline__ void sincos_f64(double x, double* s, double* c) { sincos(x, s, c); }
-
-// u = (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x)
-__device__ __forceinline__ void abc_field(const Abc& p, double x, double y, double z, double& u0,
-                                          double& u1, double& u2) {
+// sin and cos of the three coordinates of a point.
+struct Trig3 {
   double sx, cx, sy, cy, sz, cz;
-  sincos_f64(x, &sx, &cx);
-  sincos_f64(y, &sy, &cy);
-  sincos_f64(z, &sz, &cz);
-  u0 = p.A * sz + p.C * cy;
-  u1 = p.B * sx + p.A * cz;
-  u2 = p.C * sy + p.B * cx;
+};
+
+__device__ __forceinline__ Trig3 trig3(double x, double y, double z) {
+  Trig3 t;
+  trig::sincos_fast(x, &t.sx, &t.cx);
+  trig::sincos_fast(y, &t.sy, &t.cy);
+  trig::sincos_fast(z, &t.sz, &t.cz);
+  return t;
 }
 
-// One explicit-midpoint step without wrap: k1 = u(x), xm = x + (dt/2) k1,
-// x <- x + dt u(xm).
+// The same for the point (x + dx, y + dy, z + dz), from the values at (x, y, z).
+__device__ __forceinline__ Trig3 trig3_shift(const Trig3& t, double x, double y, double z,
+                                             double dx, double dy, double dz) {
+  Trig3 r;
+  trig::sincos_shift(x, t.sx, t.cx, dx, &r.sx, &r.cx);
+  trig::sincos_shift(y, t.sy, t.cy, dy, &r.sy, &r.cy);
+  trig::sincos_shift(z, t.sz, t.cz, dz, &r.sz, &r.cz);
+  return r;
+}
+
+// u = (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x)
+__device__ __forceinline__ void field_of(const Abc& p, const Trig3& t, double& u0, double& u1,
+                                         double& u2) {
+  u0 = p.A * t.sz + p.C * t.cy;
+  u1 = p.B * t.sx + p.A * t.cz;
+  u2 = p.C * t.sy + p.B * t.cx;
+}
+
+__device__ __forceinline__ void abc_field(const Abc& p, double x, double y, double z, double& u0,
+                                          double& u1, double& u2) {
+  field_of(p, trig3(x, y, z), u0, u1, u2);
+}
+
+// One explicit-midpoint step: k1 = u(x), xm = x + (dt/2) k1, k2 = u(xm),
+// x+ = x + dt k2.  On return x holds x+ (not wrapped), t the sines and
+// cosines at the start point and d = dt k2 the displacement.
+__device__ __forceinline__ void rk2_midpoint_parts(const Abc& p, double dt, double& x, double& y,
+                                                   double& z, Trig3& t, double& d0, double& d1,
+                                                   double& d2) {
+  t = trig3(x, y, z);
+  double k0, k1, k2;
+  field_of(p, t, k0, k1, k2);
+  const double h = 0.5 * dt;
+  const Trig3 tm = trig3_shift(t, x, y, z, h * k0, h * k1, h * k2);
+  field_of(p, tm, k0, k1, k2);
+  d0 = dt * k0;
+  d1 = dt * k1;
+  d2 = dt * k2;
+  x = x + d0;
+  y = y + d1;
+  z = z + d2;
+}
+
+// One explicit-midpoint step without wrap.
 __device__ __forceinline__ void rk2_midpoint(const Abc& p, double dt, double& x, double& y,
                                              double& z) {
-  double k0, k1, k2;
-  abc_field(p, x, y, z, k0, k1, k2);
-  const double h = 0.5 * dt;
-  const double xm = x + h * k0, ym = y + h * k1, zm = z + h * k2;
-  abc_field(p, xm, ym, zm, k0, k1, k2);
-  x = x + dt * k0;
-  y = y + dt * k1;
-  z = z + dt * k2;
+  Trig3 t;
+  double d0, d1, d2;
+  rk2_midpoint_parts(p, dt, x, y, z, t, d0, d1, d2);
 }
 
 // Alignment (bytes) of a run of VEC consecutive T starting at a multiple of
@@ -65,8 +104,6 @@ template <typename T, int VEC>
 __device__ constexpr size_t run_align() {
   return sizeof(T) * VEC < 16 ? sizeof(T) * VEC : 16;
 }
-
-__device__ __forceinline__ Abc to_abc(const AbcParams& p) { return Abc{p.A, p.B, p.C}; }
 
 template <typename T>
 __device__ __forceinline__ double widen(T v) {
@@ -99,8 +136,11 @@ __device__ __forceinline__ void update_particle(PT& x0, PT& x1, PT& x2, VT& v0, 
       v2 = static_cast<VT>(widen(v2) + dt * widen(a2));
     }
   } else {
-    double y0 = widen(x0), y1 = widen(x1), y2 = widen(x2);
-    rk2_midpoint(p, dt, y0, y1, y2);
+    const double s0 = widen(x0), s1 = widen(x1), s2 = widen(x2);
+    double y0 = s0, y1 = s1, y2 = s2;
+    Trig3 t;
+    double d0, d1, d2;
+    rk2_midpoint_parts(p, dt, y0, y1, y2, t, d0, d1, d2);
     if (wrap) {
       y0 = wrap_box(y0);
       y1 = wrap_box(y1);
@@ -109,8 +149,10 @@ __device__ __forceinline__ void update_particle(PT& x0, PT& x1, PT& x2, VT& v0, 
     x0 = static_cast<PT>(y0);
     x1 = static_cast<PT>(y1);
     x2 = static_cast<PT>(y2);
+    // the stored velocity is the field at the new position (the field is
+    // 2pi-periodic, so the shift from the start point needs no wrap)
     double u0, u1, u2;
-    abc_field(p, y0, y1, y2, u0, u1, u2);
+    field_of(p, trig3_shift(t, s0, s1, s2, d0, d1, d2), u0, u1, u2);
     v0 = static_cast<VT>(u0);
     v1 = static_cast<VT>(u1);
     v2 = static_cast<VT>(u2);

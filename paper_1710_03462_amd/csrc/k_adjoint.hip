@@ -58,33 +58,26 @@ __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
 __device__ __forceinline__ void rk2_reverse(const Abc& p, double dt, double x, double y, double z,
                                             double& l0, double& l1, double& l2, double& g0,
                                             double& g1, double& g2) {
-  double sx, cx, sy, cy, sz, cz;
-  sincos_f64(x, &sx, &cx);
-  sincos_f64(y, &sy, &cy);
-  sincos_f64(z, &sz, &cz);
+  const Trig3 t = trig3(x, y, z);
+  double k0, k1, k2;
+  field_of(p, t, k0, k1, k2);
   const double h = 0.5 * dt;
-  const double k0 = p.A * sz + p.C * cy;
-  const double k1 = p.B * sx + p.A * cz;
-  const double k2 = p.C * sy + p.B * cx;
-  double smx, cmx, smy, cmy, smz, cmz;
-  sincos_f64(x + h * k0, &smx, &cmx);
-  sincos_f64(y + h * k1, &smy, &cmy);
-  sincos_f64(z + h * k2, &smz, &cmz);
+  const Trig3 m = trig3_shift(t, x, y, z, h * k0, h * k1, h * k2);  // at xm
   // J(xm)^T lam
-  const double t0 = (p.B * cmx) * l1 - (p.B * smx) * l2;
-  const double t1 = (p.C * cmy) * l2 - (p.C * smy) * l0;
-  const double t2 = (p.A * cmz) * l0 - (p.A * smz) * l1;
+  const double t0 = (p.B * m.cx) * l1 - (p.B * m.sx) * l2;
+  const double t1 = (p.C * m.cy) * l2 - (p.C * m.sy) * l0;
+  const double t2 = (p.A * m.cz) * l0 - (p.A * m.sz) * l1;
   const double m0 = dt * t0, m1 = dt * t1, m2 = dt * t2;
   // G(xm)^T lam and G(x)^T mu
-  const double qa = smz * l0 + cmz * l1, qb = smx * l1 + cmx * l2, qc = cmy * l0 + smy * l2;
-  const double ra = sz * m0 + cz * m1, rb = sx * m1 + cx * m2, rc = cy * m0 + sy * m2;
+  const double qa = m.sz * l0 + m.cz * l1, qb = m.sx * l1 + m.cx * l2, qc = m.cy * l0 + m.sy * l2;
+  const double ra = t.sz * m0 + t.cz * m1, rb = t.sx * m1 + t.cx * m2, rc = t.cy * m0 + t.sy * m2;
   g0 = g0 + (dt * qa + h * ra);
   g1 = g1 + (dt * qb + h * rb);
   g2 = g2 + (dt * qc + h * rc);
   // J(x)^T mu
-  const double s0 = (p.B * cx) * m1 - (p.B * sx) * m2;
-  const double s1 = (p.C * cy) * m2 - (p.C * sy) * m0;
-  const double s2 = (p.A * cz) * m0 - (p.A * sz) * m1;
+  const double s0 = (p.B * t.cx) * m1 - (p.B * t.sx) * m2;
+  const double s1 = (p.C * t.cy) * m2 - (p.C * t.sy) * m0;
+  const double s2 = (p.A * t.cz) * m0 - (p.A * t.sz) * m1;
   l0 = l0 + m0 + h * s0;
   l1 = l1 + m1 + h * s1;
   l2 = l2 + m2 + h * s2;

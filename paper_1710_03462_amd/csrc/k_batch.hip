@@ -38,7 +38,7 @@ __device__ __forceinline__ void store_vec(T* p, const T (&v)[VEC]) {
 }
 
 template <typename VT, int PPT>
-__global__ __launch_bounds__(1024) void batch_rk2_kernel(BatchLaunch b) {
+__global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
   for (int64_t t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
     const BatchSet& S = b.sets[b.tile_set[t]];
     const Abc p{S.A, S.B, S.C};

@@ -823,8 +823,8 @@ void soax_batch_destroy(soax_batch* b) {
 
 soax_status soax_batch_config(soax_batch* b, int32_t block, int32_t per_thread, int32_t blocks_per_cu) {
   if (!b) return fail(SOAX_E_ARG, "batch is NULL");
-  if (block != 0 && (block < 64 || block > 1024 || block % 64))
-    return fail(SOAX_E_ARG, "block %d must be 0 or a multiple of 64 in 64..1024", block);
+  if (block != 0 && (block < 64 || block > 512 || block % 64))
+    return fail(SOAX_E_ARG, "block %d must be 0 or a multiple of 64 in 64..512", block);
   if (per_thread != 0 && per_thread != 1 && per_thread != 2 && per_thread != 4)
     return fail(SOAX_E_ARG, "per_thread %d must be 0, 1, 2 or 4", per_thread);
   if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(SOAX_E_ARG, "blocks_per_cu must be 0..64");

@@ -1,0 +1,142 @@
+// trig.h -- fp64 sine and cosine for the hot path.
+//
+// sincos_fast(x): both functions of one argument.  Positions on the hot path
+// stay within a few box edges of the origin, so the full-range reduction of
+// the device math library (Payne-Hanek) is replaced for |x| <= 2^19 by the
+// Cody-Waite method (W. J. Cody and W. Waite, "Software Manual for the
+// Elementary Functions", 1980):
+//   k = nearest integer to x * 2/pi,  r = x - k*pi/2  with pi/2 split into
+//   three doubles (the first two with 33 significant bits, so k*part is exact
+//   for |k| < 2^20; constants derived by gen_trig_constants.py),
+// followed by the Taylor series of sin and cos on |r| <= pi/4, truncated
+// after r^15 and r^16 (the first omitted terms are below 5e-17 relative),
+// evaluated by Horner's rule.  The quadrant k mod 4 picks and signs the
+// results.  Arguments outside that range, infinities and NaNs go to the
+// device library's sincos.
+//
+// sincos_shift(x, sin x, cos x, d): both functions of x + d for a small shift
+// |d| <= 1/8, by the angle-addition formulas with sin d and cos d - 1 from
+// their Taylor series (truncated after d^9 and d^10; omitted terms below
+// 3e-17 relative).  A time step moves a particle by dt*u, far less than 1/8,
+// so the midpoint and end-point values of a step come from the start-point
+// values without a second reduction; larger shifts fall back to
+// sincos_fast(x + d).  The shift uses the exact sum x + d, which differs from
+// the rounded sum by at most half an ulp of x.
+//
+// Every result is within about one ulp of the exact value (checked against
+// glibc / long double on the host).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace soax {
+namespace trig {
+
+constexpr double kPio2Hi = 0x1.921fb54400000p+0;
+constexpr double kPio2Mid = 0x1.0b4611a600000p-34;
+constexpr double kPio2Lo = 0x1.3198a2e037073p-69;
+constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+constexpr double kFastMax = 0x1p19;
+constexpr double kShiftMax = 0.125;
+
+// 1/n! rounded once: n! is exact in a double for n <= 18.
+constexpr double inv_fact(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return 1.0 / f;
+}
+
+// sin r = r + r^3 (S1 + w (S2 + ... + w^5 S7)),  w = r^2
+constexpr double S1 = -inv_fact(3), S2 = inv_fact(5), S3 = -inv_fact(7), S4 = inv_fact(9),
+                 S5 = -inv_fact(11), S6 = inv_fact(13), S7 = -inv_fact(15);
+// cos r = 1 - w/2 + w^2 (C1 + w (C2 + ... + w^5 C7))
+constexpr double C1 = inv_fact(4), C2 = -inv_fact(6), C3 = inv_fact(8), C4 = -inv_fact(10),
+                 C5 = inv_fact(12), C6 = -inv_fact(14), C7 = inv_fact(16);
+
+// a*b + k with one rounding, k a compile-time constant.  On the GPU the
+// constant is passed as a scalar-register operand of a three-operand fma, so
+// no vector register has to be loaded with it first.
+__host__ __device__ __forceinline__ double fma_k(double a, double b, double k) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+#else
+  return fma(a, b, k);
+#endif
+}
+
+struct SinCos {
+  double s, c;
+};
+
+// Out-of-range arguments: kept out of line so the fast path stays small.  The
+// pair is returned by value so that the caller's results never have to live
+// in memory.
+inline __host__ __device__ __attribute__((noinline)) SinCos sincos_wide(double x) {
+  SinCos r;
+  sincos(x, &r.s, &r.c);
+  return r;
+}
+
+__host__ __device__ __forceinline__ void sincos_fast(double x, double* s, double* c) {
+  if (!(fabs(x) <= kFastMax)) {
+    const SinCos r = sincos_wide(x);
+    *s = r.s;
+    *c = r.c;
+    return;
+  }
+  const double k = rint(x * kTwoOverPi);
+  double r = fma(-k, kPio2Hi, x);  // exact
+  r = fma(-k, kPio2Mid, r);
+  r = fma(-k, kPio2Lo, r);
+  const double w = r * r;
+  double ps = w * S7 + S6;  // the lowest-order rounding is far below the result's ulp
+  ps = fma_k(w, ps, S5);
+  ps = fma_k(w, ps, S4);
+  ps = fma_k(w, ps, S3);
+  ps = fma_k(w, ps, S2);
+  ps = fma_k(w, ps, S1);
+  const double sr = fma(r * w, ps, r);
+  double pc = w * C7 + C6;
+  pc = fma_k(w, pc, C5);
+  pc = fma_k(w, pc, C4);
+  pc = fma_k(w, pc, C3);
+  pc = fma_k(w, pc, C2);
+  pc = fma_k(w, pc, C1);
+  const double cr = fma(w, fma(w, pc, -0.5), 1.0);
+  // x = k pi/2 + r:  sin x = (sr, cr, -sr, -cr)[k mod 4], cos x = (cr, -sr, -cr, sr)[k mod 4]
+  const int q = static_cast<int>(k);
+  const double a = (q & 1) ? cr : sr;
+  const double b = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -a : a;
+  *c = ((q + 1) & 2) ? -b : b;
+}
+
+// sin d = d + d^3 (T1 + w (T2 + w (T3 + w T4)))
+constexpr double T1 = -inv_fact(3), T2 = inv_fact(5), T3 = -inv_fact(7), T4 = inv_fact(9);
+// cos d - 1 = w (-1/2 + w (U1 + w (U2 + w (U3 + w U4))))
+constexpr double U1 = inv_fact(4), U2 = -inv_fact(6), U3 = inv_fact(8), U4 = -inv_fact(10);
+
+__host__ __device__ __forceinline__ void sincos_shift(double x, double sx, double cx, double d,
+                                                      double* s, double* c) {
+  if (!(fabs(d) <= kShiftMax)) {
+    sincos_fast(x + d, s, c);
+    return;
+  }
+  const double w = d * d;
+  double p = w * T4 + T3;
+  p = fma_k(w, p, T2);
+  p = fma_k(w, p, T1);
+  const double sd = fma(d * w, p, d);
+  double q = w * U4 + U3;
+  q = fma_k(w, q, U2);
+  q = fma_k(w, q, U1);
+  const double cm1 = w * fma(w, q, -0.5);
+  // sin(x+d) = sin x + (sin x (cos d - 1) + cos x sin d), likewise for cos
+  *s = fma(cx, sd, fma(sx, cm1, sx));
+  *c = fma(-sx, sd, fma(cx, cm1, cx));
+}
+
+}  // namespace trig
+}  // namespace soax

@@ -1,0 +1,67 @@
+// Host-side check of the library's fp64 sincos (trig.h) against glibc:
+// prints the largest error in ulps of the glibc value over seeded arguments.
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include "trig.h"
+
+static double ulp_of(double v) {
+  double a = fabs(v);
+  if (a < 0x1p-1022) return 0x1p-1074;
+  return nextafter(a, INFINITY) - a;
+}
+
+int main(int argc, char** argv) {
+  const double lo = argc > 1 ? atof(argv[1]) : -1.0;
+  const double hi = argc > 2 ? atof(argv[2]) : 8.0;
+  const long n = argc > 3 ? atol(argv[3]) : 1000000;
+  uint64_t st = 0x9E3779B97F4A7C15ull;
+  double worst_s = 0, worst_c = 0, at_s = 0, at_c = 0;
+  for (long i = 0; i < n + 16; ++i) {
+    double x;
+    if (i < 16) {  // quadrant boundaries and special points
+      const double pts[16] = {0.0, -0.0, 1e-300, 1e-8, M_PI / 4, M_PI / 2, M_PI, 3 * M_PI / 2,
+                              2 * M_PI, 6.283185307179586, -M_PI / 2, 5e-324, 1.0, -1.0,
+                              3.141592653589793, 7.0};
+      x = pts[i];
+    } else {
+      st += 0x9E3779B97F4A7C15ull;
+      uint64_t z = st;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      z ^= z >> 31;
+      x = lo + (hi - lo) * ((z >> 11) * 0x1p-53);
+    }
+    double s, c;
+    soax::trig::sincos_fast(x, &s, &c);
+    const double es = fabs(s - sin(x)) / ulp_of(sin(x));
+    const double ec = fabs(c - cos(x)) / ulp_of(cos(x));
+    if (es > worst_s) { worst_s = es; at_s = x; }
+    if (ec > worst_c) { worst_c = ec; at_c = x; }
+  }
+  // shifted evaluation: sin/cos(x + d) from sin/cos(x), reference in long double;
+  // the error is absolute, in units of ulp(1) = 2^-52
+  double worst_ss = 0, worst_sc = 0;
+  for (long i = 0; i < n; ++i) {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double x = lo + (hi - lo) * ((z >> 11) * 0x1p-53);
+    const double d = ((z & 0x7ff) ? 0.25 : 0.01) * (((z >> 11) & 0xfffff) * 0x1p-20 - 0.5);
+    double s, c, s2, c2;
+    soax::trig::sincos_fast(x, &s, &c);
+    soax::trig::sincos_shift(x, s, c, d, &s2, &c2);
+    const long double xl = (long double)x + (long double)d;
+    const double rs = (double)sinl(xl), rc = (double)cosl(xl);
+    // angle addition bounds the absolute error: measure it in ulps of 1
+    const double es = fabs(s2 - rs) / 0x1p-52, ec = fabs(c2 - rc) / 0x1p-52;
+    if (es > worst_ss) worst_ss = es;
+    if (ec > worst_sc) worst_sc = ec;
+  }
+  printf("%.3f %.17g %.3f %.17g %.3f %.3f\n", worst_s, at_s, worst_c, at_c, worst_ss, worst_sc);
+  return 0;
+}
