@@ -48,14 +48,18 @@ __device__ __forceinline__ Trig3 trig3(double x, double y, double z) {
 }
 
 // The same for the point (x + dx, y + dy, z + dz), from the values at (x, y, z).
+// SMALL: the caller guarantees every shift is at most trig::kShiftMax.
+template <bool SMALL>
 __device__ __forceinline__ Trig3 trig3_shift(const Trig3& t, double x, double y, double z,
                                              double dx, double dy, double dz) {
   Trig3 r;
-  trig::sincos_shift(x, t.sx, t.cx, dx, &r.sx, &r.cx);
-  trig::sincos_shift(y, t.sy, t.cy, dy, &r.sy, &r.cy);
-  trig::sincos_shift(z, t.sz, t.cz, dz, &r.sz, &r.cz);
+  trig::sincos_shift<!SMALL>(x, t.sx, t.cx, dx, &r.sx, &r.cx);
+  trig::sincos_shift<!SMALL>(y, t.sy, t.cy, dy, &r.sy, &r.cy);
+  trig::sincos_shift<!SMALL>(z, t.sz, t.cz, dz, &r.sz, &r.cz);
   return r;
 }
+
+static_assert(kShiftLimit == trig::kShiftMax, "small_steps must match the shift bound");
 
 // u = (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x)
 __device__ __forceinline__ void field_of(const Abc& p, const Trig3& t, double& u0, double& u1,
@@ -73,6 +77,7 @@ __device__ __forceinline__ void abc_field(const Abc& p, double x, double y, doub
 // One explicit-midpoint step: k1 = u(x), xm = x + (dt/2) k1, k2 = u(xm),
 // x+ = x + dt k2.  On return x holds x+ (not wrapped), t the sines and
 // cosines at the start point and d = dt k2 the displacement.
+template <bool SMALL>
 __device__ __forceinline__ void rk2_midpoint_parts(const Abc& p, double dt, double& x, double& y,
                                                    double& z, Trig3& t, double& d0, double& d1,
                                                    double& d2) {
@@ -80,7 +85,7 @@ __device__ __forceinline__ void rk2_midpoint_parts(const Abc& p, double dt, doub
   double k0, k1, k2;
   field_of(p, t, k0, k1, k2);
   const double h = 0.5 * dt;
-  const Trig3 tm = trig3_shift(t, x, y, z, h * k0, h * k1, h * k2);
+  const Trig3 tm = trig3_shift<SMALL>(t, x, y, z, h * k0, h * k1, h * k2);
   field_of(p, tm, k0, k1, k2);
   d0 = dt * k0;
   d1 = dt * k1;
@@ -91,11 +96,12 @@ __device__ __forceinline__ void rk2_midpoint_parts(const Abc& p, double dt, doub
 }
 
 // One explicit-midpoint step without wrap.
+template <bool SMALL>
 __device__ __forceinline__ void rk2_midpoint(const Abc& p, double dt, double& x, double& y,
                                              double& z) {
   Trig3 t;
   double d0, d1, d2;
-  rk2_midpoint_parts(p, dt, x, y, z, t, d0, d1, d2);
+  rk2_midpoint_parts<SMALL>(p, dt, x, y, z, t, d0, d1, d2);
 }
 
 // Alignment (bytes) of a run of VEC consecutive T starting at a multiple of
@@ -111,8 +117,8 @@ __device__ __forceinline__ double widen(T v) {
 }
 
 // Advance one particle.  Positions and velocities are widened to double,
-// combined in double and rounded back on store.
-template <int INTEG, typename PT, typename VT>
+// combined in double and rounded back on store.  SMALL: small_steps holds.
+template <int INTEG, typename PT, typename VT, bool SMALL>
 __device__ __forceinline__ void update_particle(PT& x0, PT& x1, PT& x2, VT& v0, VT& v1, VT& v2,
                                                 VT a0, VT a1, VT a2, double dt, const Abc& p,
                                                 int wrap) {
@@ -140,7 +146,7 @@ __device__ __forceinline__ void update_particle(PT& x0, PT& x1, PT& x2, VT& v0, 
     double y0 = s0, y1 = s1, y2 = s2;
     Trig3 t;
     double d0, d1, d2;
-    rk2_midpoint_parts(p, dt, y0, y1, y2, t, d0, d1, d2);
+    rk2_midpoint_parts<SMALL>(p, dt, y0, y1, y2, t, d0, d1, d2);
     if (wrap) {
       y0 = wrap_box(y0);
       y1 = wrap_box(y1);
@@ -152,7 +158,7 @@ __device__ __forceinline__ void update_particle(PT& x0, PT& x1, PT& x2, VT& v0, 
     // the stored velocity is the field at the new position (the field is
     // 2pi-periodic, so the shift from the start point needs no wrap)
     double u0, u1, u2;
-    field_of(p, trig3_shift(t, s0, s1, s2, d0, d1, d2), u0, u1, u2);
+    field_of(p, trig3_shift<SMALL>(t, s0, s1, s2, d0, d1, d2), u0, u1, u2);
     v0 = static_cast<VT>(u0);
     v1 = static_cast<VT>(u1);
     v2 = static_cast<VT>(u2);

@@ -25,6 +25,7 @@ constexpr int kRedBlock = 256;  // workgroup size of every reducing kernel
 
 
 
+template <bool SMALL>
 __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
       until_ckpt = a.k;
     }
     --until_ckpt;
-    rk2_midpoint(p, a.dt, x, y, z);
+    rk2_midpoint<SMALL>(p, a.dt, x, y, z);
   }
   a.xT[0][i] = x;
   a.xT[1][i] = y;
@@ -55,6 +56,7 @@ __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
 //   g  += dt G(xm)^T lam+ + (dt/2) G(x)^T mu
 //   lam = lam+ + mu + (dt/2) J(x)^T mu
 // where J = du/dx and G = du/d(A,B,C).
+template <bool SMALL>
 __device__ __forceinline__ void rk2_reverse(const Abc& p, double dt, double x, double y, double z,
                                             double& l0, double& l1, double& l2, double& g0,
                                             double& g1, double& g2) {
@@ -62,7 +64,7 @@ __device__ __forceinline__ void rk2_reverse(const Abc& p, double dt, double x, d
   double k0, k1, k2;
   field_of(p, t, k0, k1, k2);
   const double h = 0.5 * dt;
-  const Trig3 m = trig3_shift(t, x, y, z, h * k0, h * k1, h * k2);  // at xm
+  const Trig3 m = trig3_shift<SMALL>(t, x, y, z, h * k0, h * k1, h * k2);  // at xm
   // J(xm)^T lam
   const double t0 = (p.B * m.cx) * l1 - (p.B * m.sx) * l2;
   const double t1 = (p.C * m.cy) * l2 - (p.C * m.sy) * l0;
@@ -107,7 +109,7 @@ __device__ __forceinline__ void block_sum3(double v0, double v1, double v2, doub
 }
 
 // KM: states held in registers per (sub-)segment.
-template <int KM>
+template <int KM, bool SMALL>
 __global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const Abc p = to_abc(a.abc);
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
       const int64_t nsub = (len + KM - 1) / KM;
       for (int64_t q = nsub - 1; q >= 0; --q) {
         double x = cp[0], y = cp[n], z = cp[2 * n];
-        for (int64_t s = 0; s < q * KM; ++s) rk2_midpoint(p, dt, x, y, z);
+        for (int64_t s = 0; s < q * KM; ++s) rk2_midpoint<SMALL>(p, dt, x, y, z);
         const int m = static_cast<int>(min(static_cast<int64_t>(KM), len - q * KM));
         double sx[KM], sy[KM], sz[KM];
 #pragma unroll
@@ -132,12 +134,12 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
             sx[j] = x;
             sy[j] = y;
             sz[j] = z;
-            if (j + 1 < m) rk2_midpoint(p, dt, x, y, z);
+            if (j + 1 < m) rk2_midpoint<SMALL>(p, dt, x, y, z);
           }
         }
 #pragma unroll
         for (int j = KM - 1; j >= 0; --j) {
-          if (j < m) rk2_reverse(p, dt, sx[j], sy[j], sz[j], l0, l1, l2, g0, g1, g2);
+          if (j < m) rk2_reverse<SMALL>(p, dt, sx[j], sy[j], sz[j], l0, l1, l2, g0, g1, g2);
         }
       }
     }
@@ -199,7 +201,10 @@ __global__ __launch_bounds__(kRedBlock) void sqdist_kernel(LossArgs a) {
 hipError_t launch_rk2_forward_ckpt(const CkptArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   const int64_t grid = (a.n + 255) / 256;
-  hipLaunchKernelGGL(rk2_ckpt_kernel, dim3(grid), dim3(256), 0, s, a);
+  if (small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C))
+    hipLaunchKernelGGL(rk2_ckpt_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(rk2_ckpt_kernel<false>, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -208,12 +213,21 @@ int64_t adjoint_partials(int64_t n) { return (n + kRedBlock - 1) / kRedBlock; }
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s) {
   const int64_t grid = adjoint_partials(a.n);
   if (grid > 0) {
-    if (a.k <= 8)
-      hipLaunchKernelGGL((adjoint_kernel<8>), dim3(grid), dim3(kRedBlock), 0, s, a);
-    else if (a.k <= 20)
-      hipLaunchKernelGGL((adjoint_kernel<20>), dim3(grid), dim3(kRedBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((adjoint_kernel<32>), dim3(grid), dim3(kRedBlock), 0, s, a);
+    if (small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C)) {
+      if (a.k <= 8)
+        hipLaunchKernelGGL((adjoint_kernel<8, true>), dim3(grid), dim3(kRedBlock), 0, s, a);
+      else if (a.k <= 20)
+        hipLaunchKernelGGL((adjoint_kernel<20, true>), dim3(grid), dim3(kRedBlock), 0, s, a);
+      else
+        hipLaunchKernelGGL((adjoint_kernel<32, true>), dim3(grid), dim3(kRedBlock), 0, s, a);
+    } else {
+      if (a.k <= 8)
+        hipLaunchKernelGGL((adjoint_kernel<8, false>), dim3(grid), dim3(kRedBlock), 0, s, a);
+      else if (a.k <= 20)
+        hipLaunchKernelGGL((adjoint_kernel<20, false>), dim3(grid), dim3(kRedBlock), 0, s, a);
+      else
+        hipLaunchKernelGGL((adjoint_kernel<32, false>), dim3(grid), dim3(kRedBlock), 0, s, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

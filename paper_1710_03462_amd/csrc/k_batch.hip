@@ -37,7 +37,7 @@ __device__ __forceinline__ void store_vec(T* p, const T (&v)[VEC]) {
   }
 }
 
-template <typename VT, int PPT>
+template <typename VT, int PPT, bool SMALL>
 __global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
   for (int64_t t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
     const BatchSet& S = b.sets[b.tile_set[t]];
@@ -59,8 +59,8 @@ __global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         u[j] = v[j] = w[j] = VT(0);
-        update_particle<kRk2Abc, double, VT>(x[j], y[j], z[j], u[j], v[j], w[j], VT(0), VT(0),
-                                             VT(0), dt, p, 1);
+        update_particle<kRk2Abc, double, VT, SMALL>(x[j], y[j], z[j], u[j], v[j], w[j], VT(0),
+                                                    VT(0), VT(0), dt, p, 1);
       }
       store_vec<double, PPT>(px + i0, x);
       store_vec<double, PPT>(py + i0, y);
@@ -72,7 +72,8 @@ __global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
       for (int64_t i = i0; i < S.n; ++i) {
         double x = px[i], y = py[i], z = pz[i];
         VT u = VT(0), v = VT(0), w = VT(0);
-        update_particle<kRk2Abc, double, VT>(x, y, z, u, v, w, VT(0), VT(0), VT(0), dt, p, 1);
+        update_particle<kRk2Abc, double, VT, SMALL>(x, y, z, u, v, w, VT(0), VT(0), VT(0), dt, p,
+                                                    1);
         px[i] = x;
         py[i] = y;
         pz[i] = z;
@@ -84,17 +85,17 @@ __global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
   }
 }
 
-template <typename VT>
+template <typename VT, bool SMALL>
 hipError_t batch_t(const BatchLaunch& b, hipStream_t s) {
   switch (b.per_thread) {
     case 1:
-      hipLaunchKernelGGL((batch_rk2_kernel<VT, 1>), dim3(b.grid), dim3(b.block), 0, s, b);
+      hipLaunchKernelGGL((batch_rk2_kernel<VT, 1, SMALL>), dim3(b.grid), dim3(b.block), 0, s, b);
       break;
     case 2:
-      hipLaunchKernelGGL((batch_rk2_kernel<VT, 2>), dim3(b.grid), dim3(b.block), 0, s, b);
+      hipLaunchKernelGGL((batch_rk2_kernel<VT, 2, SMALL>), dim3(b.grid), dim3(b.block), 0, s, b);
       break;
     default:
-      hipLaunchKernelGGL((batch_rk2_kernel<VT, 4>), dim3(b.grid), dim3(b.block), 0, s, b);
+      hipLaunchKernelGGL((batch_rk2_kernel<VT, 4, SMALL>), dim3(b.grid), dim3(b.block), 0, s, b);
       break;
   }
   return hipGetLastError();
@@ -104,7 +105,8 @@ hipError_t batch_t(const BatchLaunch& b, hipStream_t s) {
 
 hipError_t launch_batch_rk2(const BatchLaunch& b, hipStream_t s) {
   if (b.ntiles == 0) return hipSuccess;
-  return b.vel_t == kF64 ? batch_t<double>(b, s) : batch_t<float>(b, s);
+  if (b.small) return b.vel_t == kF64 ? batch_t<double, true>(b, s) : batch_t<float, true>(b, s);
+  return b.vel_t == kF64 ? batch_t<double, false>(b, s) : batch_t<float, false>(b, s);
 }
 
 }  // namespace soax

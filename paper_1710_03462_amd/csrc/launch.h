@@ -30,6 +30,17 @@ struct AbcParams {
   double A, B, C;
 };
 
+// Largest displacement per coordinate for which a step's midpoint and end
+// point sines come from its start point by angle addition without a check.
+constexpr double kShiftLimit = 0.125;
+
+// True when every displacement of a midpoint step, (dt/2) u and dt u, is at
+// most kShiftLimit in each coordinate, since |u_i| <= |A| + |B| + |C|.
+inline __host__ __device__ bool small_steps(double dt, double A, double B, double C) {
+  const double s = (A < 0 ? -A : A) + (B < 0 ? -B : B) + (C < 0 ? -C : C);
+  return (dt < 0 ? -dt : dt) * s <= kShiftLimit;
+}
+
 // ------------------------------------------------------------------ steps
 
 struct SoaStepArgs {
@@ -174,6 +185,7 @@ struct BatchLaunch {
   int32_t per_thread;
   int32_t grid;
   int32_t vel_t;
+  int32_t small;  // small_steps holds for every set
 };
 hipError_t launch_batch_rk2(const BatchLaunch& b, hipStream_t s);
 

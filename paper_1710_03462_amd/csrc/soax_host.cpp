@@ -161,7 +161,8 @@ struct soax_batch {
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
   hipStream_t capture_stream = nullptr;
-  std::map<std::tuple<int64_t, int, int, int>, hipGraphExec_t> graphs;
+  int small = 0;  // small_steps holds for every set's current dt and amplitudes
+  std::map<std::tuple<int64_t, int, int, int, int>, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -427,7 +428,8 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
     a.dt = dt;
     a.abc = abc;
     a.wrap = wrap;
-    int vec = set->vec ? set->vec : 4;
+    // RK2 is VALU-heavy: one particle per thread keeps more waves resident
+    int vec = set->vec ? set->vec : (integrator == SOAX_RK2_ABC ? 1 : 4);
     if (!set->soa_vec_ok) vec = 1;
     const int block = set->block[SOAX_SOA] ? set->block[SOAX_SOA] : 256;
     for (int64_t k = 0; k < nsteps; ++k)
@@ -672,6 +674,7 @@ BatchLaunch batch_launch(const soax_batch* b) {
   if (grid > b->ntiles) grid = b->ntiles;
   L.grid = static_cast<int32_t>(std::max<int64_t>(grid, 1));
   L.vel_t = b->vel_t;
+  L.small = b->small;
   return L;
 }
 
@@ -681,7 +684,9 @@ soax_status upload_params(soax_batch* b, const double* dt, const double* abc, hi
     HIP_TRY(hipEventSynchronize(b->stage_done), "hipEventSynchronize");
     b->stage_pending = false;
   }
+  int small = 1;
   for (size_t i = 0; i < b->sets.size(); ++i) {
+    if (!small_steps(dt[i], abc[3 * i], abc[3 * i + 1], abc[3 * i + 2])) small = 0;
     b->stage[i].dt = dt[i];
     b->stage[i].A = abc[3 * i];
     b->stage[i].B = abc[3 * i + 1];
@@ -692,6 +697,7 @@ soax_status upload_params(soax_batch* b, const double* dt, const double* abc, hi
           "hipMemcpyAsync(set table)");
   HIP_TRY(hipEventRecord(b->stage_done, s), "hipEventRecord");
   b->stage_pending = true;
+  b->small = small;
   return SOAX_OK;
 }
 
@@ -709,14 +715,13 @@ soax_status per_set_step(soax_batch* b, const double* dt, const double* abc, hip
     a.dt = dt[i];
     a.abc = AbcParams{abc[3 * i], abc[3 * i + 1], abc[3 * i + 2]};
     a.wrap = 1;
-    const int vec = set->soa_vec_ok ? 4 : 1;
-    HIP_TRY(launch_soa_step(kRk2Abc, kF64, b->vel_t, vec, 256, a, s), "per-set step launch");
+    HIP_TRY(launch_soa_step(kRk2Abc, kF64, b->vel_t, 1, 256, a, s), "per-set step launch");
   }
   return SOAX_OK;
 }
 
 soax_status graph_for(soax_batch* b, int64_t nsteps, hipGraphExec_t* out) {
-  auto key = std::make_tuple(nsteps, b->block, b->per_thread, b->blocks_per_cu);
+  auto key = std::make_tuple(nsteps, b->block, b->per_thread, b->blocks_per_cu, b->small);
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) {
     *out = it->second;

@@ -118,11 +118,15 @@ constexpr double T1 = -inv_fact(3), T2 = inv_fact(5), T3 = -inv_fact(7), T4 = in
 // cos d - 1 = w (-1/2 + w (U1 + w (U2 + w (U3 + w U4))))
 constexpr double U1 = inv_fact(4), U2 = -inv_fact(6), U3 = inv_fact(8), U4 = -inv_fact(10);
 
+// CHECKED = false: the caller guarantees |d| <= kShiftMax.
+template <bool CHECKED = true>
 __host__ __device__ __forceinline__ void sincos_shift(double x, double sx, double cx, double d,
                                                       double* s, double* c) {
-  if (!(fabs(d) <= kShiftMax)) {
-    sincos_fast(x + d, s, c);
-    return;
+  if constexpr (CHECKED) {
+    if (!(fabs(d) <= kShiftMax)) {
+      sincos_fast(x + d, s, c);
+      return;
+    }
   }
   const double w = d * d;
   double p = w * T4 + T3;

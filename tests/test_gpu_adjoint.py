@@ -56,6 +56,18 @@ def test_forward_adjoint_match_oracle(ref, n, nsteps, k):
     check_grads(gx, gabc, rgx, rgabc)
 
 
+@pytest.mark.parametrize("dt", [0.05, 0.1])
+def test_large_steps_match_oracle(ref, dt):
+    # dt * (A+B+C) > 1/8: checked shifts with full-reduction fallback
+    n, nsteps, k = 600, 30, 7
+    x0, target = si.adjoint_inputs(n, seed=8)
+    xT, tape, loss, gx, gabc = gpu_fwd_bwd(x0, target, ABC, dt, nsteps, k)
+    rxT, states, rloss, rgx, rgabc = ref_fwd_bwd(ref, x0, target, ABC, dt, nsteps)
+    assert np.abs(xT - rxT).max() <= 1e-12 * L
+    assert abs(loss - rloss) <= 1e-12 * abs(rloss)
+    check_grads(gx, gabc, rgx, rgabc)
+
+
 def test_gradients_bit_identical_for_every_k():
     n, nsteps, dt = 1500, 200, 5e-3
     x0, target = si.adjoint_inputs(n, seed=5)

@@ -60,6 +60,22 @@ def test_batch_matches_oracle(ref, mode):
             assert_fields_close(g[4 + d], want[4 + d])
 
 
+def test_one_large_step_set_switches_to_checked_kernel(ref):
+    sets, states = make_sets(SIZES)
+    dts, abc = plan(len(SIZES))
+    dts = dts.copy()
+    dts[3] = 0.2  # dt * (A+B+C) > 1/8 for this set only
+    soax.Batch(sets).step(dts, abc, 6, mode=soax.GRAPH)
+    got = download(sets)
+    sch = ref.Schema(si.BASE_FIELDS)
+    for s, (arrays, g) in enumerate(zip(states, got)):
+        want = [a.copy() for a in arrays]
+        ref.step_soa(sch, want, ref.RK2_ABC, dts[s], 6, abc=abc[s], wrap=True)
+        for d in range(3):
+            assert_positions_close(g[1 + d], want[1 + d])
+            assert_fields_close(g[4 + d], want[4 + d])
+
+
 def test_modes_and_single_sets_bit_identical():
     dts, abc = plan(len(SIZES))
     results = []

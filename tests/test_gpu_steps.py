@@ -303,3 +303,18 @@ def test_copy_kernel():
     soax.copy(dst8, src8)
     _sync()
     assert torch.equal(dst8[:1000], src8) and not dst8[1000:].any()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("dt", [0.05, 0.1, 0.3])
+def test_rk2_large_steps_use_checked_shifts(ref, layout, dt):
+    # dt * (|A|+|B|+|C|) > 1/8: the kernels check every shift and some exceed
+    # the angle-addition range, falling back to a full reduction
+    n = 3001
+    arrays = si.random_state(si.BASE_FIELDS, n, seed=77)
+    abc = [1.0, 1.0, 1.0]
+    got = run_gpu(si.BASE_FIELDS, arrays, layout, "rk2_abc", dt, 12, abc=abc)
+    want = run_ref(ref, si.BASE_FIELDS, arrays, ref.RK2_ABC, dt, 12, abc=abc)
+    for d in range(3):
+        assert_positions_close(got[1 + d], want[1 + d])
+        assert_fields_close(got[4 + d], want[4 + d])
