@@ -314,23 +314,16 @@ __device__ __forceinline__ void copy_elem(char* dst, const char* src, int es) {
   }
 }
 
-// Walk the tile's SoA side in 16-byte chunks: chunk w belongs to the array
-// `arr` with sum_{b<arr} tile*es_b/16 <= w, and covers 16/es elements.
-struct ChunkCursor {
-  int arr = 0;
-  int base = 0;
-};
-
-__device__ __forceinline__ bool seek_chunk(const XposeArgs& t, int tile, int w, ChunkCursor& c) {
-  while (c.arr < t.narrays) {
-    const int nch = (tile * t.es[c.arr]) >> 4;
-    if (w < c.base + nch) return true;
-    c.base += nch;
-    ++c.arr;
-  }
-  return false;
+// Element of width es at `src` (es = 1, 4 or 8) copied to `dst`.
+template <bool ALIGNED>
+__device__ __forceinline__ void copy_es(char* dst, const char* src, int es) {
+  copy_elem<ALIGNED>(dst, src, es);
 }
 
+// AoS -> SoA: the tile's records are staged through LDS with coalesced 16-byte
+// loads; then, array by array (a loop uniform across the workgroup), thread r
+// moves element r from its record in LDS to the array, so consecutive lanes
+// store consecutive elements.
 template <bool ALIGNED>
 __global__ __launch_bounds__(256) void aos_to_soa_kernel(const XposeArgs* __restrict__ tp,
                                                          int tile) {
@@ -342,27 +335,19 @@ __global__ __launch_bounds__(256) void aos_to_soa_kernel(const XposeArgs* __rest
   const int stride = t.stride;
   stage_in(lds, t.aos + r0 * stride, nrec * stride);
   __syncthreads();
-  if (nrec == tile) {
-    ChunkCursor c;
-    for (int w = threadIdx.x; seek_chunk(t, tile, w, c); w += blockDim.x) {
-      const int es = t.es[c.arr];
-      const int per = 16 / es;
-      const int e0 = (w - c.base) * per;
-      const char* src = lds + e0 * stride + t.off[c.arr];
-      uint4 val;
-      char* vb = reinterpret_cast<char*>(&val);
-      for (int q = 0; q < per; ++q) copy_elem<ALIGNED>(vb + q * es, src + q * stride, es);
-      *reinterpret_cast<uint4*>(t.soa[c.arr] + (r0 + e0) * es) = val;
-    }
-  } else {
-    for (int w = threadIdx.x; w < nrec * t.narrays; w += blockDim.x) {
-      const int arr = w / nrec, e = w - arr * nrec;
-      const int es = t.es[arr];
-      copy_elem<ALIGNED>(t.soa[arr] + (r0 + e) * es, lds + e * stride + t.off[arr], es);
-    }
+  const int na = t.narrays;
+  for (int a = 0; a < na; ++a) {
+    const int es = t.es[a];
+    const int off = t.off[a];
+    char* dst = t.soa[a] + r0 * es;
+    for (int r = threadIdx.x; r < nrec; r += blockDim.x)
+      copy_es<ALIGNED>(dst + r * es, lds + r * stride + off, es);
   }
 }
 
+// SoA -> AoS: zero the LDS tile (padding bytes are whatever no field writes),
+// scatter every array's elements into their records, then store the tile with
+// coalesced 16-byte stores.
 template <bool ALIGNED>
 __global__ __launch_bounds__(256) void soa_to_aos_kernel(const XposeArgs* __restrict__ tp,
                                                          int tile) {
@@ -373,27 +358,16 @@ __global__ __launch_bounds__(256) void soa_to_aos_kernel(const XposeArgs* __rest
   const int nrec = static_cast<int>(min(static_cast<int64_t>(tile), t.n - r0));
   const int stride = t.stride;
   const int nbytes = nrec * stride;
-  // padding bytes are whatever no field writes: zero them first
   for (int c = threadIdx.x; c < (nbytes + 15) >> 4; c += blockDim.x)
     lds_u4[c] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
-  if (nrec == tile) {
-    ChunkCursor c;
-    for (int w = threadIdx.x; seek_chunk(t, tile, w, c); w += blockDim.x) {
-      const int es = t.es[c.arr];
-      const int per = 16 / es;
-      const int e0 = (w - c.base) * per;
-      const uint4 val = *reinterpret_cast<const uint4*>(t.soa[c.arr] + (r0 + e0) * es);
-      const char* vb = reinterpret_cast<const char*>(&val);
-      char* dst = lds + e0 * stride + t.off[c.arr];
-      for (int q = 0; q < per; ++q) copy_elem<ALIGNED>(dst + q * stride, vb + q * es, es);
-    }
-  } else {
-    for (int w = threadIdx.x; w < nrec * t.narrays; w += blockDim.x) {
-      const int arr = w / nrec, e = w - arr * nrec;
-      const int es = t.es[arr];
-      copy_elem<ALIGNED>(lds + e * stride + t.off[arr], t.soa[arr] + (r0 + e) * es, es);
-    }
+  const int na = t.narrays;
+  for (int a = 0; a < na; ++a) {
+    const int es = t.es[a];
+    const int off = t.off[a];
+    const char* src = t.soa[a] + r0 * es;
+    for (int r = threadIdx.x; r < nrec; r += blockDim.x)
+      copy_es<ALIGNED>(lds + r * stride + off, src + r * es, es);
   }
   __syncthreads();
   stage_out(t.aos + r0 * stride, lds, nbytes);
