@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1710_03462_amd", "csrc", f)
-                  for f in ("k_step.hip", "device_math.h")]
+                  for f in ("k_step.hip", "device_math.h", "trig.h", "launch.h")]
 
 
 def log(*a):
@@ -274,7 +274,7 @@ def main():
     per_launch = t.ms / (args.steps * nsteps)
     log(f"[bench] SoA RK2: {value:.4e} updates/s, {per_launch:.3f} ms/launch")
 
-    kname = "soa_step_kernel<RK2_ABC,double,float,4>"
+    kname = "soa_step_kernel<RK2_ABC,double,float,1>"
     traffic = traffic_from_profiles(kname, "hbm_bytes_per_launch")
     roofline = {"kernel": kname, "bound": "hbm", "achieved": gbs(60 * n, per_launch),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
