@@ -100,6 +100,22 @@ def bench_euler(torch, soax, ps, n, nsteps, layout):
             "frac_of_peak": gbs(phys * n, per_launch) / HBM_PEAK_GBS, "steps": nsteps}
 
 
+def bench_small_euler(torch, soax, si, n=100_000, nsteps=100):
+    """The 1e5-particle Euler workload: 4 MB of state, cache-resident and
+    launch-bound, reported as updates/s in every layout."""
+    ps = soax.ParticleSet(si.BASE_FIELDS, n)
+    ps.fill(seed=0)
+    ps.soa_to_aos()
+    out = {"n": n, "nsteps": nsteps}
+    for lay in ("soa", "aos", "aos_naive"):
+        ps.step(lay, "euler", 1e-3, 10, wrap=True)
+        with Timer(torch) as t:
+            ps.step(lay, "euler", 1e-3, nsteps, wrap=True)
+        out[lay] = {"updates_per_s": rate(n * nsteps, t.ms), "us_per_step": t.ms * 1e3 / nsteps}
+    ps.close()
+    return out
+
+
 def bench_copy(torch, soax, nbytes=4 << 30):
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -137,6 +153,37 @@ def bench_wide(torch, soax, si, n):
                           "physical_GBps": gbs(phys_x * n, t3.ms)}}
     ps.close()
     return res
+
+
+def bench_remove(torch, soax, si, n, frac=0.01, reps=3):
+    """Removal by overwriting with the last particle on both copies of the
+    headline set: a seeded 1% of the particles flagged.  Each repetition
+    first regrows the set to n (untimed)."""
+    ps = soax.ParticleSet(si.BASE_FIELDS, n)
+    ps.fill(seed=0, vel_mode=1, abc=[1, 1, 1])
+    ps.soa_to_aos()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    flags = (torch.rand(n, generator=g, device="cuda") < frac).to(torch.uint8)
+    m = int(flags.sum())
+    n_new = n - m
+    moves = int(flags[:n_new].sum())  # flagged slots below the new size
+    times = []
+    for _ in range(reps + 1):
+        ps.resize(n)
+        with Timer(torch) as t:
+            got = ps.remove_flagged(flags)
+        assert got == n_new
+        times.append(t.ms)
+    ms = min(times[1:])
+    # algorithmic bytes: every flag read once; every moved particle read and
+    # written in both copies (40 B SoA + 48 B AoS record)
+    alg = n + moves * 2 * (ps.soa_bytes + ps.stride)
+    out = {"n": n, "removed": m, "moves": moves, "ms": ms, "alg_GBps": gbs(alg, ms),
+           "particles_per_s": rate(n, ms)}
+    ps.close()
+    del flags
+    return out
 
 
 def bench_adjoint(torch, soax, si, n, nsteps=200, k=20):
@@ -198,6 +245,43 @@ def bench_batch(torch, soax, si, nsets=256, nsteps=100):
     return res
 
 
+def bench_sweep(torch, soax, si, sizes=(0, 4, 8, 16, 32),
+                ns=(1_000, 10_000, 100_000, 1_000_000, 10_000_000, 100_000_000)):
+    """The paper's GPU experiment (Section 3.2) on this GPU: the Euler step of
+    Listing 4's particle (float x[3], v[3], temp[SIZE]) in SoA, LDS-staged AoS
+    and per-thread AoS (the paper's access pattern), time per particle-step
+    against the particle count N.  Algorithmic bytes per particle-step: 36
+    (x and v read, x written); the AoS copies move whole records (2 * stride)."""
+    rows = []
+    for size in sizes:
+        fields = si.particle_size_fields(size)
+        for n in ns:
+            ps = soax.ParticleSet(fields, n)
+            ps.fill(seed=0)
+            ps.soa_to_aos()
+            nsteps = max(20, min(2000, int(2e8 // n)))
+            row = {"SIZE": size, "N": n, "record_bytes": ps.stride, "nsteps": nsteps}
+            for lay in ("soa", "aos", "aos_naive"):
+                ps.step(lay, "euler", 1e-3, 5, wrap=False)
+                with Timer(torch) as t:
+                    ps.step(lay, "euler", 1e-3, nsteps, wrap=False)
+                per = t.ms / nsteps
+                row[lay] = {"ns_per_particle": per * 1e6 / n,
+                            "alg_GBps": gbs(36 * n, per),
+                            "physical_GBps": gbs((36 if lay == "soa" else 2 * ps.stride) * n, per)}
+            row["aos_over_soa"] = row["aos"]["ns_per_particle"] / row["soa"]["ns_per_particle"]
+            row["naive_over_soa"] = (row["aos_naive"]["ns_per_particle"] /
+                                     row["soa"]["ns_per_particle"])
+            log(f"[sweep] SIZE={size:2d} N={n:>9d}  soa {row['soa']['ns_per_particle']:.4f} ns  "
+                f"aos {row['aos']['ns_per_particle']:.4f}  naive "
+                f"{row['aos_naive']['ns_per_particle']:.4f}")
+            rows.append(row)
+            ps.close()
+            del ps
+            torch.cuda.empty_cache()
+    return rows
+
+
 def cpu_baseline(ref, si, target_s=10.0):
     """The oracle's RK2 SoA step on a bounded sample of the headline workload."""
     sch = ref.Schema(si.BASE_FIELDS)
@@ -238,8 +322,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=float, default=1e8, help="particles of the headline workload")
     ap.add_argument("--rows", default="all",
-                    help="comma list of extra rows: aos,euler,copy,wide,adjoint,batch | all | none")
+                    help="comma list of extra rows: aos,euler,small,copy,wide,adjoint,batch,"
+                         "remove | all | none")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run only the N x SIZE sweep of the paper's GPU experiment and print "
+                         "its rows as one JSON line")
+    ap.add_argument("--sweep-sizes", default="0,4,8,16,32")
+    ap.add_argument("--sweep-ns", default="1e3,1e4,1e5,1e6,1e7,1e8")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -254,7 +344,14 @@ def main():
 
     soax.lib()
     torch.cuda.set_device(0)
-    rows = {"aos", "euler", "copy", "wide", "adjoint", "batch"} if args.rows == "all" else \
+    if args.sweep:
+        sizes = tuple(int(x) for x in args.sweep_sizes.split(","))
+        ns = tuple(int(float(x)) for x in args.sweep_ns.split(","))
+        print(json.dumps({"sweep": bench_sweep(torch, soax, si, sizes, ns),
+                          "device": torch.cuda.get_device_name(0)}), flush=True)
+        return 0
+    rows = {"aos", "euler", "small", "copy", "wide", "adjoint", "batch", "remove"} \
+        if args.rows == "all" else \
         set() if args.rows == "none" else set(args.rows.split(","))
     n = int(args.n)
     nsteps = 50
@@ -298,6 +395,9 @@ def main():
     ps.close()
     del ps
     torch.cuda.empty_cache()
+    if "small" in rows:
+        log("[bench] 1e5-particle Euler workload")
+        out_rows["euler_1e5"] = bench_small_euler(torch, soax, si)
     if "copy" in rows:
         log("[bench] copy ceiling")
         out_rows["copy"] = bench_copy(torch, soax)
@@ -310,6 +410,9 @@ def main():
     if "batch" in rows:
         log("[bench] batched sets")
         out_rows["batch"] = bench_batch(torch, soax, si)
+    if "remove" in rows:
+        log("[bench] removal by overwriting with the last particle")
+        out_rows["remove"] = bench_remove(torch, soax, si, n)
     torch.cuda.empty_cache()
 
     cpu = None

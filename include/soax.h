@@ -122,6 +122,13 @@ soax_status soax_create(const soax_schema* schema, int64_t n, soax_set** out);
 soax_status soax_bind(const soax_schema* schema, int64_t n, void* const* soa_ptrs, void* aos_ptr,
                       soax_set** out);
 
+/* soax_bind for buffers with room for `capacity` >= n particles (each SoA
+ * array capacity elements, the AoS buffer capacity records), so that the set
+ * can grow up to capacity in place (soax_resize, soax_push_back).  soax_bind
+ * is this call with capacity = n. */
+soax_status soax_bind_capacity(const soax_schema* schema, int64_t n, int64_t capacity,
+                               void* const* soa_ptrs, void* aos_ptr, soax_set** out);
+
 /* Free a set (and the memory it owns).  NULL is ignored.  Does not sync. */
 void soax_destroy(soax_set* set);
 
@@ -171,6 +178,62 @@ soax_status soax_soa_to_aos(soax_set* set, void* stream);
 /* Copy record i of one layout (SOAX_SOA or SOAX_AOS) to host memory in AoS
  * form (stride bytes, padding 0).  Synchronises the null stream. */
 soax_status soax_get_record(const soax_set* set, int32_t layout, int64_t i, void* host_record);
+
+/* ------------------------------------------------------------ containers */
+
+/*
+ * Container operations (the container interface of Section 4.1: resize,
+ * element access, push_back; removal of Section 2).  They apply to every copy
+ * the set has (SoA and AoS), keep each particle's bytes unchanged and leave
+ * the two copies consistent if they were.  A set that changes its size or
+ * buffers (any call below but soax_capacity and soax_set_record) invalidates
+ * every batch that holds it: such a batch's calls then fail with STATE.
+ * All of them synchronise `stream` before returning.
+ */
+
+/* Host query of the particle count and the capacity. */
+soax_status soax_capacity(const soax_set* set, int64_t* n, int64_t* capacity);
+
+/* Room for `capacity` particles.  Owned sets (soax_create) move to larger
+ * buffers, copying their n particles; bound sets fail with STATE beyond the
+ * capacity they were bound with.  Never shrinks.  Errors: ARG, RANGE, STATE,
+ * OOM, HIP. */
+soax_status soax_reserve(soax_set* set, int64_t capacity, void* stream);
+
+/* New particle count n.  Particles [old n, n) are zero bytes in every copy;
+ * shrinking drops the tail.  Owned sets grow to max(n, 2 * capacity) when
+ * needed.  Errors: ARG, RANGE, STATE (bound set beyond its capacity), OOM, HIP. */
+soax_status soax_resize(soax_set* set, int64_t n, void* stream);
+
+/* Append `count` records given in AoS form in host memory (count * stride
+ * bytes, the set's schema and packing): the AoS copy receives the bytes as
+ * they are, the SoA copy each field component.  Grows like soax_resize.
+ * The host buffer may be reused when the call returns. */
+soax_status soax_push_back(soax_set* set, const void* host_records, int64_t count, void* stream);
+
+/* Move a bound set to caller buffers with room for `capacity` >= n
+ * particles (the same copies as before: soa_ptrs NULL iff the set has no SoA
+ * copy, aos_ptr NULL iff it has no AoS copy), copying its n particles; the
+ * old buffers may be freed when the call returns.  Owned sets fail with
+ * STATE.  Errors: ARG, RANGE, LAYOUT, STATE, HIP. */
+soax_status soax_rebind(soax_set* set, int64_t capacity, void* const* soa_ptrs, void* aos_ptr,
+                        void* stream);
+
+/* Write record i (0 <= i < n) of every copy from one AoS-form host record.
+ * Synchronous (null stream). */
+soax_status soax_set_record(soax_set* set, int64_t i, const void* host_record);
+
+/*
+ * Remove every particle i < n with flags[i] != 0 (device, n bytes; not
+ * modified) by overwriting it with the last particle, the removal of
+ * Section 2 for sets whose order does not matter.  The result equals the
+ * sequential rule "while particle i is flagged, copy the last particle over
+ * it and drop the last", computed as: the flagged slots below n' = n - m
+ * (m flagged particles) in ascending order receive the unflagged particles
+ * at or above n' in descending order.  Writes n' to *new_n (host).
+ * Errors: ARG, HIP, OOM.
+ */
+soax_status soax_remove_flagged(soax_set* set, const uint8_t* flags, int64_t* new_n, void* stream);
 
 /* ------------------------------------------------ differentiable advection */
 

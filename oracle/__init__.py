@@ -49,6 +49,8 @@ def lib():
         L.soaxref_draw.restype = ctypes.c_uint64
         L.soaxref_fill.argtypes = [sp, i64, ctypes.c_uint64, i32, vp, vp]
         L.soaxref_fill_range.argtypes = [sp, i64, i64, ctypes.c_uint64, i32, vp, vp]
+        L.soaxref_remove_flagged.argtypes = [sp, i64, vp, vp]
+        L.soaxref_remove_flagged.restype = i64
         L.soaxref_field.argtypes = [vp, vp, vp]
         L.soaxref_field.restype = None
         L.soaxref_step_soa.argtypes = [sp, i64, vp, i32, dbl, i64, vp, i32]
@@ -153,6 +155,19 @@ def fill_range(schema, first, count, seed=0, vel_mode=0, abc=None):
                                     ap if abc is not None else None, _ptrs(arrays)),
            "soaxref_fill_range")
     return arrays
+
+
+def remove_flagged(schema, arrays, flags):
+    """Sequential removal by overwriting with the last particle; returns the
+    surviving prefix of every array (copies) and the new count."""
+    arrays = [a.copy() for a in arrays]
+    fl = np.ascontiguousarray(flags, dtype=np.uint8).copy()
+    n = len(fl)
+    m = lib().soaxref_remove_flagged(schema.ref, n, _ptrs(arrays) if arrays else None,
+                                     fl.ctypes.data)
+    if m < 0:
+        raise ValueError("soaxref_remove_flagged failed")
+    return [a[:m] for a in arrays], m
 
 
 def field(abc, x):

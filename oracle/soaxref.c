@@ -309,6 +309,38 @@ int soaxref_soa_to_aos(const ref_schema* s, int64_t n, void* const* soa, void* a
   return 0;
 }
 
+/* ------------------------------------------------------------- containers */
+
+/*
+ * Removal without keeping the order (Section 2, the paragraph on std::vector
+ * vs std::list: a particle is removed by overwriting it with the last
+ * particle).  Sequentially, for i = 0, 1, ...: while particle i is flagged and
+ * i < n, copy particle n-1 (and its flag) over it and shrink n by one.
+ * flags[] is updated alongside; returns the new count.
+ */
+int64_t soaxref_remove_flagged(const ref_schema* s, int64_t n, void* const* soa, uint8_t* flags) {
+  if (check_schema(s) || n < 0 || !soa || (!flags && n > 0)) return -1;
+  int64_t i = 0;
+  while (i < n) {
+    if (!flags[i]) {
+      ++i;
+      continue;
+    }
+    const int64_t last = n - 1;
+    if (last != i) {
+      for (int f = 0; f < s->nfields; ++f) {
+        int64_t es = esize(s->dtypes[f]);
+        int a = first_array(s, f);
+        for (int c = 0; c < s->dims[f]; ++c)
+          memcpy((char*)soa[a + c] + i * es, (const char*)soa[a + c] + last * es, es);
+      }
+      flags[i] = flags[last];
+    }
+    n = last;
+  }
+  return n;
+}
+
 /* -------------------------------------------------------------------- fill */
 
 static const uint64_t GOLDEN_GAMMA = 0x9E3779B97F4A7C15ULL;

@@ -74,6 +74,10 @@ int soaxref_step_soa(const ref_schema* s, int64_t n, void* const* soa, int integ
 int soaxref_step_aos(const ref_schema* s, int64_t n, void* aos, int integrator,
                      double dt, int64_t nsteps, const double* abc, int wrap);
 
+/* Remove flagged particles by overwriting each with the last particle
+ * (Section 2); returns the new count (negative on bad arguments). */
+int64_t soaxref_remove_flagged(const ref_schema* s, int64_t n, void* const* soa, uint8_t* flags);
+
 /* Bulk layout transposes; soa_to_aos writes every padding byte as 0. */
 int soaxref_aos_to_soa(const ref_schema* s, int64_t n, const void* aos, void* const* soa);
 int soaxref_soa_to_aos(const ref_schema* s, int64_t n, void* const* soa, void* aos);

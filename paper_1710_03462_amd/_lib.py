@@ -86,6 +86,14 @@ def lib():
         "soax_batch_config": [vp, i32, i32, i32],
         "soax_batch_get_config": [vp, vp, vp, vp],
         "soax_batch_tune": [vp, ctypes.c_char_p],
+        "soax_bind_capacity": [sp, i64, i64, vp, vp, vp],
+        "soax_capacity": [vp, vp, vp],
+        "soax_reserve": [vp, i64, vp],
+        "soax_resize": [vp, i64, vp],
+        "soax_push_back": [vp, vp, i64, vp],
+        "soax_rebind": [vp, i64, vp, vp, vp],
+        "soax_set_record": [vp, i64, vp],
+        "soax_remove_flagged": [vp, vp, vp, vp],
         "soax_copy": [vp, vp, i64, vp],
         "soax_strerror": [i32],
         "soax_last_error": [],

@@ -111,9 +111,87 @@ __device__ constexpr size_t run_align() {
   return sizeof(T) * VEC < 16 ? sizeof(T) * VEC : 16;
 }
 
+// Vector of VEC elements of T (VEC = 1: T itself).
+template <typename T, int VEC>
+struct VecOf {
+  typedef T type __attribute__((ext_vector_type(VEC)));
+};
+template <typename T>
+struct VecOf<T, 1> {
+  typedef T type;
+};
+
+// A run of VEC consecutive elements moved as chunks of at most 16 bytes.
+// NT: nontemporal hint, for streams that are not touched again soon: large
+// read-only inputs and every output of a step whose data far exceeds the
+// caches (measured on the MI355X: an in-place Euler step at 1e8 particles
+// goes from 5.3 to 6.4 TB/s with nontemporal velocity loads and stores).
+template <typename T, int VEC>
+struct RunChunk {
+  static constexpr int kBytes = sizeof(T) * VEC < 16 ? static_cast<int>(sizeof(T)) * VEC : 16;
+  static constexpr int kElems = kBytes / static_cast<int>(sizeof(T));
+  static constexpr int kChunks = VEC / kElems;
+  using V = typename VecOf<T, kElems>::type;
+};
+
+template <bool NT, typename T, int VEC>
+__device__ __forceinline__ void ld_run(const T* p, T (&v)[VEC]) {
+  using C = RunChunk<T, VEC>;
+#pragma unroll
+  for (int c = 0; c < C::kChunks; ++c) {
+    const typename C::V* q = reinterpret_cast<const typename C::V*>(p + c * C::kElems);
+    typename C::V t;
+    if constexpr (NT)
+      t = __builtin_nontemporal_load(q);
+    else
+      t = *q;
+    __builtin_memcpy(&v[c * C::kElems], &t, C::kBytes);
+  }
+}
+
+template <bool NT, typename T, int VEC>
+__device__ __forceinline__ void st_run(T* p, const T (&v)[VEC]) {
+  using C = RunChunk<T, VEC>;
+#pragma unroll
+  for (int c = 0; c < C::kChunks; ++c) {
+    typename C::V* q = reinterpret_cast<typename C::V*>(p + c * C::kElems);
+    typename C::V t;
+    __builtin_memcpy(&t, &v[c * C::kElems], C::kBytes);
+    if constexpr (NT)
+      __builtin_nontemporal_store(t, q);
+    else
+      *q = t;
+  }
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ T ld1(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ void st1(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 template <typename T>
 __device__ __forceinline__ double widen(T v) {
   return static_cast<double>(v);
+}
+
+// One component of an Euler step (eq. (1)): the new position, and for
+// EULER_ACC the new velocity from the acceleration.  The same arithmetic as
+// update_particle, one coordinate at a time.
+template <int INTEG, typename PT, typename VT>
+__device__ __forceinline__ void euler_component(PT& x, VT& v, VT a, double dt, int wrap) {
+  double y = widen(x) + dt * widen(v);
+  if constexpr (std::is_same<PT, double>::value) {
+    if (wrap) y = wrap_box(y);
+  }
+  x = static_cast<PT>(y);
+  if constexpr (INTEG == kEulerAcc) v = static_cast<VT>(widen(v) + dt * widen(a));
 }
 
 // Advance one particle.  Positions and velocities are widened to double,

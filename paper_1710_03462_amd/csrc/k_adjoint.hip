@@ -35,19 +35,19 @@ __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
   const int64_t n = a.n;
   int64_t until_ckpt = 0;
   for (int64_t s = 0; s < a.nsteps; ++s) {
-    if (until_ckpt == 0) {
-      tp[0] = x;
-      tp[n] = y;
-      tp[2 * n] = z;
+    if (until_ckpt == 0) {  // the tape is written once and read back much later
+      st1<true>(tp, x);
+      st1<true>(tp + n, y);
+      st1<true>(tp + 2 * n, z);
       tp += 3 * n;
       until_ckpt = a.k;
     }
     --until_ckpt;
     rk2_midpoint<SMALL>(p, a.dt, x, y, z);
   }
-  a.xT[0][i] = x;
-  a.xT[1][i] = y;
-  a.xT[2][i] = z;
+  st1<true>(a.xT[0] + i, x);
+  st1<true>(a.xT[1] + i, y);
+  st1<true>(a.xT[2] + i, z);
 }
 
 // Reverse one midpoint step taken from state (x, y, z).  With

@@ -19,24 +19,6 @@ namespace soax {
 
 namespace {
 
-template <typename T, int VEC>
-__device__ __forceinline__ void load_vec(const T* p, T (&v)[VEC]) {
-  if constexpr (VEC == 1) {
-    v[0] = *p;
-  } else {
-    __builtin_memcpy(v, __builtin_assume_aligned(p, run_align<T, VEC>()), sizeof(T) * VEC);
-  }
-}
-
-template <typename T, int VEC>
-__device__ __forceinline__ void store_vec(T* p, const T (&v)[VEC]) {
-  if constexpr (VEC == 1) {
-    *p = v[0];
-  } else {
-    __builtin_memcpy(__builtin_assume_aligned(p, run_align<T, VEC>()), v, sizeof(T) * VEC);
-  }
-}
-
 template <typename VT, int PPT, bool SMALL>
 __global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
   for (int64_t t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
@@ -53,21 +35,22 @@ __global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
     if (i0 + PPT <= S.n) {
       double x[PPT], y[PPT], z[PPT];
       VT u[PPT], v[PPT], w[PPT];
-      load_vec<double, PPT>(px + i0, x);
-      load_vec<double, PPT>(py + i0, y);
-      load_vec<double, PPT>(pz + i0, z);
+      ld_run<false, double, PPT>(px + i0, x);
+      ld_run<false, double, PPT>(py + i0, y);
+      ld_run<false, double, PPT>(pz + i0, z);
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         u[j] = v[j] = w[j] = VT(0);
         update_particle<kRk2Abc, double, VT, SMALL>(x[j], y[j], z[j], u[j], v[j], w[j], VT(0),
                                                     VT(0), VT(0), dt, p, 1);
       }
-      store_vec<double, PPT>(px + i0, x);
-      store_vec<double, PPT>(py + i0, y);
-      store_vec<double, PPT>(pz + i0, z);
-      store_vec<VT, PPT>(vx + i0, u);
-      store_vec<VT, PPT>(vy + i0, v);
-      store_vec<VT, PPT>(vz + i0, w);
+      // the batch spans far more than the caches: nontemporal stores
+      st_run<true, double, PPT>(px + i0, x);
+      st_run<true, double, PPT>(py + i0, y);
+      st_run<true, double, PPT>(pz + i0, z);
+      st_run<true, VT, PPT>(vx + i0, u);
+      st_run<true, VT, PPT>(vy + i0, v);
+      st_run<true, VT, PPT>(vz + i0, w);
     } else {
       for (int64_t i = i0; i < S.n; ++i) {
         double x = px[i], y = py[i], z = pz[i];

@@ -1,0 +1,208 @@
+// k_container.hip -- gfx950 kernels for the container operations of a
+// particle set: removal by overwriting with the last particle (Section 2),
+// and the zero fill used when a set grows.
+//
+// Removal is the sequential algorithm "while particle i is flagged, copy the
+// last particle over it and shrink the set", computed in parallel from its
+// closed form: with m flagged particles and n' = n - m survivors, the flagged
+// slots below n' (ascending) receive the unflagged particles at or above n'
+// taken from the end (descending).  Three passes: per-tile flag counts (the
+// host turns them into tile offsets), per-element ranks into two lists
+// (holes and movers), and the moves themselves, array by array.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "launch.h"
+
+namespace soax {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 16;  // elements per thread per tile
+constexpr int64_t kTile = int64_t(kBlock) * kItems;
+
+__global__ __launch_bounds__(kBlock) void count_flags_kernel(const uint8_t* __restrict__ flags,
+                                                             int64_t n,
+                                                             int32_t* __restrict__ counts) {
+  __shared__ int32_t red[kBlock];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + threadIdx.x * kItems;
+  int32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = base + j;
+    if (i < n && flags[i]) ++c;
+  }
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[blockIdx.x] = red[0];
+}
+
+// Exclusive scan of v over the workgroup; returns this thread's prefix and
+// writes the total to *total.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* total) {
+  __shared__ int32_t sc[kBlock];
+  sc[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int32_t add = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
+    __syncthreads();
+    sc[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const int32_t incl = sc[threadIdx.x];
+  *total = sc[kBlock - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// holes_before[b]: flagged slots in tiles before b; movers_after[b]:
+// unflagged particles in tiles after b -- both from the host's scan of the
+// counts.  Each thread walks its kItems elements in order, so ranks inside a
+// tile come from two workgroup scans.
+__global__ __launch_bounds__(kBlock) void rank_kernel(const uint8_t* __restrict__ flags, int64_t n,
+                                                      int64_t n_new,
+                                                      const int64_t* __restrict__ holes_before,
+                                                      const int64_t* __restrict__ movers_after,
+                                                      int64_t* __restrict__ hole_at,
+                                                      int64_t* __restrict__ mover_at,
+                                                      int64_t* __restrict__ nmoves) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + threadIdx.x * kItems;
+  uint32_t f = 0;  // bit j: element base + j is flagged (in-range elements only)
+  int32_t nf = 0, nu = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = base + j;
+    if (i < n) {
+      if (flags[i]) {
+        f |= 1u << j;
+        ++nf;
+      } else {
+        ++nu;
+      }
+    }
+  }
+  int32_t tot_f, tot_u;
+  const int32_t pre_f = block_exclusive_scan(nf, &tot_f);
+  const int32_t pre_u = block_exclusive_scan(nu, &tot_u);
+  int64_t hole = holes_before[blockIdx.x] + pre_f;  // flagged slots before element i
+  int32_t upto_u = pre_u;                           // unflagged in the tile up to element i
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t i = base + j;
+    if (i >= n) break;
+    if (f & (1u << j)) {
+      if (i < n_new) hole_at[hole] = i;
+      ++hole;
+    } else {
+      ++upto_u;
+      if (i >= n_new) mover_at[movers_after[blockIdx.x] + (tot_u - upto_u)] = i;
+    }
+    // the flagged slots below n_new are the first `hole` ones once i = n_new - 1
+    if (i == n_new - 1) *nmoves = hole;
+  }
+}
+
+struct alignas(16) Word16 {
+  uint32_t v[4];
+};
+
+template <int W>
+struct WordOf;
+template <>
+struct WordOf<1> {
+  using T = uint8_t;
+};
+template <>
+struct WordOf<4> {
+  using T = uint32_t;
+};
+template <>
+struct WordOf<8> {
+  using T = uint64_t;
+};
+template <>
+struct WordOf<16> {
+  using T = Word16;
+};
+
+// One thread per (move, word): element hole_at[k] <- element mover_at[k],
+// words_per elements of W bytes each.  Holes lie below the new size and
+// movers at or above it, so no thread reads what another writes.
+template <int W>
+__global__ __launch_bounds__(kBlock) void move_kernel(char* __restrict__ arr, int64_t stride,
+                                                      int words_per,
+                                                      const int64_t* __restrict__ hole_at,
+                                                      const int64_t* __restrict__ mover_at,
+                                                      const int64_t* __restrict__ nmoves) {
+  using T = typename WordOf<W>::T;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t k = t / words_per;
+  const int w = static_cast<int>(t - k * words_per);
+  if (k >= *nmoves) return;
+  T* dst = reinterpret_cast<T*>(arr + hole_at[k] * stride) + w;
+  const T* src = reinterpret_cast<const T*>(arr + mover_at[k] * stride) + w;
+  *dst = *src;
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(char* __restrict__ p, int64_t bytes) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < bytes) p[i] = 0;
+}
+
+}  // namespace
+
+int64_t container_tile_size() { return kTile; }
+
+int64_t container_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+
+hipError_t launch_count_flags(const uint8_t* flags, int64_t n, int32_t* counts, hipStream_t s) {
+  const int64_t grid = container_tiles(n);
+  if (grid > 0) hipLaunchKernelGGL(count_flags_kernel, dim3(grid), dim3(kBlock), 0, s, flags, n, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_flags(const uint8_t* flags, int64_t n, int64_t n_new,
+                             const int64_t* holes_before, const int64_t* movers_after,
+                             int64_t* hole_at, int64_t* mover_at, int64_t* nmoves, hipStream_t s) {
+  const int64_t grid = container_tiles(n);
+  if (grid > 0)
+    hipLaunchKernelGGL(rank_kernel, dim3(grid), dim3(kBlock), 0, s, flags, n, n_new, holes_before,
+                       movers_after, hole_at, mover_at, nmoves);
+  return hipGetLastError();
+}
+
+hipError_t launch_move(void* arr, int64_t stride, int word, const int64_t* hole_at,
+                       const int64_t* mover_at, const int64_t* nmoves, int64_t max_moves,
+                       hipStream_t s) {
+  if (max_moves <= 0) return hipSuccess;
+  if (word != 1 && word != 4 && word != 8 && word != 16) return hipErrorInvalidValue;
+  if (stride % word) return hipErrorInvalidValue;
+  const int words_per = static_cast<int>(stride / word);
+  const int64_t grid = (max_moves * words_per + kBlock - 1) / kBlock;
+  char* a = static_cast<char*>(arr);
+#define SOAX_MOVE(W)                                                                             \
+  hipLaunchKernelGGL(move_kernel<W>, dim3(grid), dim3(kBlock), 0, s, a, stride, words_per, hole_at, \
+                     mover_at, nmoves)
+  switch (word) {
+    case 16: SOAX_MOVE(16); break;
+    case 8: SOAX_MOVE(8); break;
+    case 4: SOAX_MOVE(4); break;
+    default: SOAX_MOVE(1); break;
+  }
+#undef SOAX_MOVE
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s) {
+  if (bytes <= 0) return hipSuccess;
+  const int64_t grid = (bytes + 255) / 256;
+  hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(256), 0, s, static_cast<char*>(p), bytes);
+  return hipGetLastError();
+}
+
+}  // namespace soax

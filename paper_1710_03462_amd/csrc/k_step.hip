@@ -30,28 +30,10 @@ constexpr int kLdsBudget = 48 * 1024;  // bytes of LDS staging per workgroup
 
 // ------------------------------------------------------------ SoA step
 
-// Load / store VEC consecutive elements (16-byte aligned when VEC > 1).
-template <typename T, int VEC>
-__device__ __forceinline__ void load_run(const T* p, T (&v)[VEC]) {
-  if constexpr (VEC == 1) {
-    v[0] = *p;
-  } else {
-    const T* q = static_cast<const T*>(__builtin_assume_aligned(p, run_align<T, VEC>()));
-    __builtin_memcpy(v, q, sizeof(T) * VEC);
-  }
-}
-
-template <typename T, int VEC>
-__device__ __forceinline__ void store_run(T* p, const T (&v)[VEC]) {
-  if constexpr (VEC == 1) {
-    *p = v[0];
-  } else {
-    T* q = static_cast<T*>(__builtin_assume_aligned(p, run_align<T, VEC>()));
-    __builtin_memcpy(q, v, sizeof(T) * VEC);
-  }
-}
-
-template <int INTEG, typename PT, typename VT, int VEC, bool SMALL>
+// STREAM: the step's arrays far exceed the caches.  Positions are loaded with
+// ordinary loads (they are overwritten in place) and every store, and the
+// loads of arrays the step only reads, carry the nontemporal hint.
+template <int INTEG, typename PT, typename VT, int VEC, bool SMALL, bool STREAM>
 __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t i0 = t * VEC;
@@ -67,23 +49,53 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
   const VT* ay = static_cast<const VT*>(a.acc[1]);
   const VT* az = static_cast<const VT*>(a.acc[2]);
   constexpr bool kReadsVel = INTEG != kRk2Abc;  // RK2 overwrites vel without reading it
+  constexpr bool kNtVelLoad = STREAM && INTEG == kEuler;  // read-only in Euler steps
 
+  if constexpr (INTEG != kRk2Abc) {
+    if (i0 + VEC <= a.n) {
+      // Euler steps are independent per coordinate: one component at a time
+      // (its loads, update and stores) keeps two or three streams per wave
+      // in flight instead of six -- faster on HBM for this in-place update.
+      PT* P[3] = {px, py, pz};
+      VT* Vv[3] = {vx, vy, vz};
+      const VT* G[3] = {ax, ay, az};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        PT x[VEC];
+        VT v[VEC], g[VEC];
+        ld_run<false, PT, VEC>(P[d] + i0, x);
+        if constexpr (INTEG == kEulerAcc) {
+          ld_run<false, VT, VEC>(Vv[d] + i0, v);
+          ld_run<STREAM, VT, VEC>(G[d] + i0, g);
+        } else {
+          ld_run<kNtVelLoad, VT, VEC>(Vv[d] + i0, v);
+        }
+#pragma unroll
+        for (int j = 0; j < VEC; ++j)
+          euler_component<INTEG, PT, VT>(x[j], v[j], INTEG == kEulerAcc ? g[j] : VT(0), a.dt,
+                                         a.wrap);
+        st_run<STREAM, PT, VEC>(P[d] + i0, x);
+        if constexpr (INTEG == kEulerAcc) st_run<STREAM, VT, VEC>(Vv[d] + i0, v);
+      }
+      return;
+    }
+  }
   if (i0 + VEC <= a.n) {
     PT x[VEC], y[VEC], z[VEC];
     VT u[VEC], v[VEC], w[VEC];
     VT ga[VEC], gb[VEC], gc[VEC];
-    load_run<PT, VEC>(px + i0, x);
-    load_run<PT, VEC>(py + i0, y);
-    load_run<PT, VEC>(pz + i0, z);
+    ld_run<false, PT, VEC>(px + i0, x);
+    ld_run<false, PT, VEC>(py + i0, y);
+    ld_run<false, PT, VEC>(pz + i0, z);
     if constexpr (kReadsVel) {
-      load_run<VT, VEC>(vx + i0, u);
-      load_run<VT, VEC>(vy + i0, v);
-      load_run<VT, VEC>(vz + i0, w);
+      ld_run<kNtVelLoad, VT, VEC>(vx + i0, u);
+      ld_run<kNtVelLoad, VT, VEC>(vy + i0, v);
+      ld_run<kNtVelLoad, VT, VEC>(vz + i0, w);
     }
     if constexpr (INTEG == kEulerAcc) {
-      load_run<VT, VEC>(ax + i0, ga);
-      load_run<VT, VEC>(ay + i0, gb);
-      load_run<VT, VEC>(az + i0, gc);
+      ld_run<STREAM, VT, VEC>(ax + i0, ga);
+      ld_run<STREAM, VT, VEC>(ay + i0, gb);
+      ld_run<STREAM, VT, VEC>(az + i0, gc);
     } else {
 #pragma unroll
       for (int j = 0; j < VEC; ++j) ga[j] = gb[j] = gc[j] = VT(0);
@@ -94,13 +106,13 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
       update_particle<INTEG, PT, VT, SMALL>(x[j], y[j], z[j], u[j], v[j], w[j], ga[j], gb[j],
                                             gc[j], a.dt, p, a.wrap);
     }
-    store_run<PT, VEC>(px + i0, x);
-    store_run<PT, VEC>(py + i0, y);
-    store_run<PT, VEC>(pz + i0, z);
+    st_run<STREAM, PT, VEC>(px + i0, x);
+    st_run<STREAM, PT, VEC>(py + i0, y);
+    st_run<STREAM, PT, VEC>(pz + i0, z);
     if constexpr (INTEG != kEuler) {
-      store_run<VT, VEC>(vx + i0, u);
-      store_run<VT, VEC>(vy + i0, v);
-      store_run<VT, VEC>(vz + i0, w);
+      st_run<STREAM, VT, VEC>(vx + i0, u);
+      st_run<STREAM, VT, VEC>(vy + i0, v);
+      st_run<STREAM, VT, VEC>(vz + i0, w);
     }
   } else {
     for (int64_t i = i0; i < a.n; ++i) {
@@ -126,20 +138,30 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
   }
 }
 
-template <int INTEG, typename PT, typename VT, bool SMALL>
+template <int INTEG, typename PT, typename VT, bool SMALL, bool STREAM>
 hipError_t soa_step_launch(int vec, int64_t grid, int block, const SoaStepArgs& a, hipStream_t s) {
   switch (vec) {
     case 1:
-      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 1, SMALL>), dim3(grid), dim3(block), 0, s, a);
+      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 1, SMALL, STREAM>), dim3(grid),
+                         dim3(block), 0, s, a);
       break;
     case 2:
-      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 2, SMALL>), dim3(grid), dim3(block), 0, s, a);
+      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 2, SMALL, STREAM>), dim3(grid),
+                         dim3(block), 0, s, a);
       break;
     default:
-      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 4, SMALL>), dim3(grid), dim3(block), 0, s, a);
+      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 4, SMALL, STREAM>), dim3(grid),
+                         dim3(block), 0, s, a);
       break;
   }
   return hipGetLastError();
+}
+
+template <int INTEG, typename PT, typename VT, bool SMALL>
+hipError_t soa_step_stream(bool stream, int vec, int64_t grid, int block, const SoaStepArgs& a,
+                           hipStream_t s) {
+  return stream ? soa_step_launch<INTEG, PT, VT, SMALL, true>(vec, grid, block, a, s)
+                : soa_step_launch<INTEG, PT, VT, SMALL, false>(vec, grid, block, a, s);
 }
 
 template <int INTEG, typename PT, typename VT>
@@ -147,11 +169,14 @@ hipError_t soa_step_vec(int vec, int block, const SoaStepArgs& a, hipStream_t s)
   const int64_t threads = (a.n + vec - 1) / vec;
   const int64_t grid = (threads + block - 1) / block;
   if (grid == 0) return hipSuccess;
+  int64_t bytes = 3 * (sizeof(PT) + sizeof(VT));
+  if (INTEG == kEulerAcc) bytes += 3 * sizeof(VT);
+  const bool stream = a.n * bytes >= kStreamBytes;
   if constexpr (INTEG == kRk2Abc) {
     if (small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C))
-      return soa_step_launch<INTEG, PT, VT, true>(vec, grid, block, a, s);
+      return soa_step_stream<INTEG, PT, VT, true>(stream, vec, grid, block, a, s);
   }
-  return soa_step_launch<INTEG, PT, VT, false>(vec, grid, block, a, s);
+  return soa_step_stream<INTEG, PT, VT, false>(stream, vec, grid, block, a, s);
 }
 
 // ------------------------------------------------------- AoS element access
@@ -208,25 +233,30 @@ __device__ __forceinline__ void update_record(char* rec, const AosStepArgs& a, c
 
 // Copy `nbytes` from global `g` (16-byte aligned) into LDS with 16-byte
 // accesses, consecutive lanes on consecutive chunks; the remainder bytewise.
+// NT: nontemporal global accesses (see ld_run).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
 __device__ __forceinline__ void stage_in(char* lds, const char* g, int nbytes) {
   const int nchunk = nbytes >> 4;
-  const uint4* src = reinterpret_cast<const uint4*>(g);
-  uint4* dst = reinterpret_cast<uint4*>(lds);
-  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) dst[c] = src[c];
+  const u32x4* src = reinterpret_cast<const u32x4*>(g);
+  u32x4* dst = reinterpret_cast<u32x4*>(lds);
+  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) dst[c] = ld1<NT>(src + c);
   for (int b = (nchunk << 4) + threadIdx.x; b < nbytes; b += blockDim.x) lds[b] = g[b];
 }
 
+template <bool NT>
 __device__ __forceinline__ void stage_out(char* g, const char* lds, int nbytes) {
   const int nchunk = nbytes >> 4;
-  const uint4* src = reinterpret_cast<const uint4*>(lds);
-  uint4* dst = reinterpret_cast<uint4*>(g);
-  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) dst[c] = src[c];
+  const u32x4* src = reinterpret_cast<const u32x4*>(lds);
+  u32x4* dst = reinterpret_cast<u32x4*>(g);
+  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) st1<NT>(dst + c, src[c]);
   for (int b = (nchunk << 4) + threadIdx.x; b < nbytes; b += blockDim.x) g[b] = lds[b];
 }
 
 // ------------------------------------------------------------- AoS steps
 
-template <int INTEG, typename PT, typename VT, bool ALIGNED, bool SMALL>
+template <int INTEG, typename PT, typename VT, bool ALIGNED, bool SMALL, bool STREAM>
 __global__ __launch_bounds__(1024) void aos_step_kernel(AosStepArgs a, int tile) {
   extern __shared__ uint4 lds_u4[];
   char* lds = reinterpret_cast<char*>(lds_u4);
@@ -234,13 +264,13 @@ __global__ __launch_bounds__(1024) void aos_step_kernel(AosStepArgs a, int tile)
   const int nrec = static_cast<int>(min(static_cast<int64_t>(tile), a.n - r0));
   char* g = a.aos + r0 * a.stride;
   const int nbytes = nrec * a.stride;
-  stage_in(lds, g, nbytes);
+  stage_in<false>(lds, g, nbytes);  // rewritten in place below
   __syncthreads();
   const Abc p = to_abc(a.abc);
   for (int r = threadIdx.x; r < nrec; r += blockDim.x)
     update_record<INTEG, PT, VT, ALIGNED, SMALL>(lds + r * a.stride, a, p);
   __syncthreads();
-  stage_out(g, lds, nbytes);
+  stage_out<STREAM>(g, lds, nbytes);
 }
 
 template <int INTEG, typename PT, typename VT, bool ALIGNED, bool SMALL>
@@ -265,12 +295,19 @@ hipError_t aos_step_launch(bool aligned, bool naive, int block, const AosStepArg
     const int tile = aos_tile_records(a.stride, block);
     const int64_t grid = (a.n + tile - 1) / tile;
     const size_t lds = (static_cast<size_t>(tile) * a.stride + 15) & ~static_cast<size_t>(15);
-    if (aligned)
-      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, true, SMALL>), dim3(grid), dim3(block),
-                         lds, s, a, tile);
+    const bool stream = a.n * a.stride >= kStreamBytes;
+    if (aligned && stream)
+      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, true, SMALL, true>), dim3(grid),
+                         dim3(block), lds, s, a, tile);
+    else if (aligned)
+      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, true, SMALL, false>), dim3(grid),
+                         dim3(block), lds, s, a, tile);
+    else if (stream)
+      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, false, SMALL, true>), dim3(grid),
+                         dim3(block), lds, s, a, tile);
     else
-      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, false, SMALL>), dim3(grid), dim3(block),
-                         lds, s, a, tile);
+      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, false, SMALL, false>), dim3(grid),
+                         dim3(block), lds, s, a, tile);
   }
   return hipGetLastError();
 }
@@ -324,7 +361,7 @@ __device__ __forceinline__ void copy_es(char* dst, const char* src, int es) {
 // loads; then, array by array (a loop uniform across the workgroup), thread r
 // moves element r from its record in LDS to the array, so consecutive lanes
 // store consecutive elements.
-template <bool ALIGNED>
+template <bool ALIGNED, bool STREAM>
 __global__ __launch_bounds__(256) void aos_to_soa_kernel(const XposeArgs* __restrict__ tp,
                                                          int tile) {
   extern __shared__ uint4 lds_u4[];
@@ -333,22 +370,32 @@ __global__ __launch_bounds__(256) void aos_to_soa_kernel(const XposeArgs* __rest
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * tile;
   const int nrec = static_cast<int>(min(static_cast<int64_t>(tile), t.n - r0));
   const int stride = t.stride;
-  stage_in(lds, t.aos + r0 * stride, nrec * stride);
+  stage_in<STREAM>(lds, t.aos + r0 * stride, nrec * stride);
   __syncthreads();
   const int na = t.narrays;
   for (int a = 0; a < na; ++a) {
     const int es = t.es[a];
     const int off = t.off[a];
     char* dst = t.soa[a] + r0 * es;
-    for (int r = threadIdx.x; r < nrec; r += blockDim.x)
-      copy_es<ALIGNED>(dst + r * es, lds + r * stride + off, es);
+    if (ALIGNED && STREAM && es == 8) {
+      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
+        st1<true>(reinterpret_cast<uint64_t*>(dst) + r,
+                  *reinterpret_cast<const uint64_t*>(lds + r * stride + off));
+    } else if (ALIGNED && STREAM && es == 4) {
+      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
+        st1<true>(reinterpret_cast<uint32_t*>(dst) + r,
+                  *reinterpret_cast<const uint32_t*>(lds + r * stride + off));
+    } else {
+      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
+        copy_es<ALIGNED>(dst + r * es, lds + r * stride + off, es);
+    }
   }
 }
 
 // SoA -> AoS: zero the LDS tile (padding bytes are whatever no field writes),
 // scatter every array's elements into their records, then store the tile with
 // coalesced 16-byte stores.
-template <bool ALIGNED>
+template <bool ALIGNED, bool STREAM>
 __global__ __launch_bounds__(256) void soa_to_aos_kernel(const XposeArgs* __restrict__ tp,
                                                          int tile) {
   extern __shared__ uint4 lds_u4[];
@@ -366,11 +413,21 @@ __global__ __launch_bounds__(256) void soa_to_aos_kernel(const XposeArgs* __rest
     const int es = t.es[a];
     const int off = t.off[a];
     const char* src = t.soa[a] + r0 * es;
-    for (int r = threadIdx.x; r < nrec; r += blockDim.x)
-      copy_es<ALIGNED>(lds + r * stride + off, src + r * es, es);
+    if (ALIGNED && STREAM && es == 8) {
+      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
+        *reinterpret_cast<uint64_t*>(lds + r * stride + off) =
+            ld1<true>(reinterpret_cast<const uint64_t*>(src) + r);
+    } else if (ALIGNED && STREAM && es == 4) {
+      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
+        *reinterpret_cast<uint32_t*>(lds + r * stride + off) =
+            ld1<true>(reinterpret_cast<const uint32_t*>(src) + r);
+    } else {
+      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
+        copy_es<ALIGNED>(lds + r * stride + off, src + r * es, es);
+    }
   }
   __syncthreads();
-  stage_out(t.aos + r0 * stride, lds, nbytes);
+  stage_out<STREAM>(t.aos + r0 * stride, lds, nbytes);
 }
 
 // ------------------------------------------------------------------- fill
@@ -448,7 +505,6 @@ __global__ __launch_bounds__(256) void vel_from_field_kernel(SoaStepArgs a) {
 // One 16-byte element per thread, nontemporal loads and stores: the fastest
 // streaming form measured on the MI355X (a grid-stride loop or several
 // elements per thread keep fewer independent requests in flight per CU).
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void copy16_kernel(u32x4* __restrict__ dst,
                                                      const u32x4* __restrict__ src, int64_t n16) {
@@ -529,17 +585,22 @@ hipError_t launch_xpose(bool to_soa, const XposeArgs& host, const XposeArgs* dev
   const int tile = xpose_tile(host.stride);
   const int64_t grid = (host.n + tile - 1) / tile;
   const size_t lds = (static_cast<size_t>(tile) * host.stride + 15) & ~static_cast<size_t>(15);
+  const bool stream = host.n * host.stride >= kStreamBytes;
+#define SOAX_XPOSE(KER)                                                                       \
+  if (host.aligned && stream)                                                                 \
+    hipLaunchKernelGGL((KER<true, true>), dim3(grid), dim3(256), lds, s, dev, tile);          \
+  else if (host.aligned)                                                                      \
+    hipLaunchKernelGGL((KER<true, false>), dim3(grid), dim3(256), lds, s, dev, tile);         \
+  else if (stream)                                                                            \
+    hipLaunchKernelGGL((KER<false, true>), dim3(grid), dim3(256), lds, s, dev, tile);         \
+  else                                                                                        \
+    hipLaunchKernelGGL((KER<false, false>), dim3(grid), dim3(256), lds, s, dev, tile);
   if (to_soa) {
-    if (host.aligned)
-      hipLaunchKernelGGL((aos_to_soa_kernel<true>), dim3(grid), dim3(256), lds, s, dev, tile);
-    else
-      hipLaunchKernelGGL((aos_to_soa_kernel<false>), dim3(grid), dim3(256), lds, s, dev, tile);
+    SOAX_XPOSE(aos_to_soa_kernel)
   } else {
-    if (host.aligned)
-      hipLaunchKernelGGL((soa_to_aos_kernel<true>), dim3(grid), dim3(256), lds, s, dev, tile);
-    else
-      hipLaunchKernelGGL((soa_to_aos_kernel<false>), dim3(grid), dim3(256), lds, s, dev, tile);
+    SOAX_XPOSE(soa_to_aos_kernel)
   }
+#undef SOAX_XPOSE
   return hipGetLastError();
 }
 

@@ -41,6 +41,11 @@ inline __host__ __device__ bool small_steps(double dt, double A, double B, doubl
   return (dt < 0 ? -dt : dt) * s <= kShiftLimit;
 }
 
+// A step whose arrays span at least this many bytes streams through HBM and
+// uses nontemporal hints; smaller working sets stay cache-resident between
+// steps and use ordinary accesses.
+constexpr int64_t kStreamBytes = int64_t(128) << 20;
+
 // ------------------------------------------------------------------ steps
 
 struct SoaStepArgs {
@@ -163,6 +168,32 @@ struct LossArgs {
 };
 int64_t loss_partials(int64_t n);
 hipError_t launch_sqdist_loss(const LossArgs& a, hipStream_t s);
+
+// ------------------------------------------------------------- containers
+
+// Removal with overwrite-by-last in three passes over a flag array (one
+// byte per particle, nonzero = remove) split into tiles of
+// container_tile_size() particles.
+int64_t container_tile_size();
+int64_t container_tiles(int64_t n);
+// counts[b] = flagged particles in tile b.
+hipError_t launch_count_flags(const uint8_t* flags, int64_t n, int32_t* counts, hipStream_t s);
+// With holes_before[b] = flagged particles in tiles before b and
+// movers_after[b] = unflagged particles in tiles after b: hole_at[k] = k-th
+// flagged slot below n_new (ascending), mover_at[k] = k-th unflagged particle
+// at or above n_new counted from the end, and *nmoves = flagged slots below
+// n_new.  Both lists need min(n - n_new, n_new) entries.
+hipError_t launch_rank_flags(const uint8_t* flags, int64_t n, int64_t n_new,
+                             const int64_t* holes_before, const int64_t* movers_after,
+                             int64_t* hole_at, int64_t* mover_at, int64_t* nmoves, hipStream_t s);
+// arr[hole_at[k]] = arr[mover_at[k]] for k < *nmoves (<= max_moves): elements
+// of `stride` bytes moved `word` bytes at a time (word divides stride and the
+// buffer's alignment; 1, 4, 8 or 16).
+hipError_t launch_move(void* arr, int64_t stride, int word, const int64_t* hole_at,
+                       const int64_t* mover_at, const int64_t* nmoves, int64_t max_moves,
+                       hipStream_t s);
+// p[0, bytes) = 0.
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
 
 // -------------------------------------------------------------- batching
 

@@ -132,8 +132,11 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 struct soax_set {
   Layout L;
   int64_t n = 0;
+  int64_t cap = 0;         // particles every buffer can hold
+  uint64_t generation = 0; // bumped whenever n or a buffer address changes
   std::vector<void*> soa;  // one per array; empty if there is no SoA copy
   char* aos = nullptr;
+  bool owns = false;       // buffers allocated (and grown) by the library
   void* owned_soa = nullptr;
   void* owned_aos = nullptr;
   bool soa_vec_ok = false;    // every SoA array 16-byte aligned
@@ -146,6 +149,7 @@ struct soax_set {
 
 struct soax_batch {
   std::vector<soax_set*> sets;
+  std::vector<uint64_t> generations;  // of each set when the batch was made
   int vel_t = kF32;
   int64_t total = 0;
   int block = 256, per_thread = 2, blocks_per_cu = 8;
@@ -178,12 +182,18 @@ soax_status check_n(const Layout& L, int64_t n) {
   return SOAX_OK;
 }
 
-// Fill the transpose table and upload it (once per set).
+// An owned set always has both copies (its buffers are null while it holds
+// room for no particle); a bound set has the copies it was given.
+bool has_soa(const soax_set* s) { return !s->soa.empty(); }
+bool has_aos(const soax_set* s) { return s->owns || s->aos != nullptr; }
+
+// Fill the transpose table from the set's buffers and size, and upload it
+// (synchronous copy; callers order it after earlier work that reads it).
 soax_status finish_set(soax_set* s) {
   s->soa_vec_ok = !s->soa.empty();
   for (void* p : s->soa)
     if (!aligned16(p)) s->soa_vec_ok = false;
-  s->aos_base_ok = s->aos && aligned16(s->aos);
+  s->aos_base_ok = s->aos ? aligned16(s->aos) : s->owns;
   XposeArgs& t = s->xpose_host;
   t.aos = s->aos;
   t.n = s->n;
@@ -199,13 +209,48 @@ soax_status finish_set(soax_set* s) {
       t.es[a] = f.es;
     }
   }
-  if (s->n > 0 && !s->soa.empty() && s->aos) {
-    void* d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(XposeArgs));
-    if (e != hipSuccess) return fail(SOAX_E_OOM, "hipMalloc(transpose table): %s", hipGetErrorString(e));
-    s->xpose_dev = static_cast<XposeArgs*>(d);
+  if (s->cap > 0 && has_soa(s) && has_aos(s)) {
+    if (!s->xpose_dev) {
+      void* d = nullptr;
+      hipError_t e = hipMalloc(&d, sizeof(XposeArgs));
+      if (e != hipSuccess) return fail(SOAX_E_OOM, "hipMalloc(transpose table): %s", hipGetErrorString(e));
+      s->xpose_dev = static_cast<XposeArgs*>(d);
+    }
     HIP_TRY(hipMemcpy(s->xpose_dev, &t, sizeof(XposeArgs), hipMemcpyHostToDevice),
             "hipMemcpy(transpose table)");
+  }
+  return SOAX_OK;
+}
+
+// Library-owned buffers for `cap` particles: one allocation holding every
+// SoA array on its own 256-byte boundary, and the AoS records.
+soax_status alloc_owned(const Layout& L, int64_t cap, void** soa_block, std::vector<void*>& soa,
+                        void** aos) {
+  *soa_block = nullptr;
+  *aos = nullptr;
+  soa.assign(L.narrays, nullptr);
+  if (cap == 0) return SOAX_OK;
+  std::vector<int64_t> off(L.narrays);
+  int64_t total = 0;
+  for (const Field& f : L.f)
+    for (int c = 0; c < f.dim; ++c) {
+      off[f.first_array + c] = total;
+      total += (cap * f.es + 255) & ~int64_t(255);
+    }
+  hipError_t e = hipMalloc(soa_block, total);
+  if (e != hipSuccess) {
+    *soa_block = nullptr;
+    return fail(SOAX_E_OOM, "hipMalloc(%lld bytes for SoA): %s", static_cast<long long>(total),
+                hipGetErrorString(e));
+  }
+  for (int a = 0; a < L.narrays; ++a) soa[a] = static_cast<char*>(*soa_block) + off[a];
+  e = hipMalloc(aos, cap * L.stride);
+  if (e != hipSuccess) {
+    (void)hipFree(*soa_block);
+    *soa_block = nullptr;
+    *aos = nullptr;
+    return fail(SOAX_E_OOM, "hipMalloc(%lld bytes for AoS): %s",
+                static_cast<long long>(cap * L.stride), hipGetErrorString(e));
   }
   return SOAX_OK;
 }
@@ -246,31 +291,41 @@ soax_status soax_create(const soax_schema* schema, int64_t n, soax_set** out) {
   soax_set* s = new soax_set();
   s->L = L;
   s->n = n;
-  s->soa.assign(L.narrays, nullptr);
-  if (n > 0) {
-    // every array on its own 256-byte boundary inside one allocation
-    std::vector<int64_t> off(L.narrays);
-    int64_t total = 0;
-    for (const Field& f : L.f)
-      for (int c = 0; c < f.dim; ++c) {
-        off[f.first_array + c] = total;
-        total += (n * f.es + 255) & ~int64_t(255);
-      }
-    hipError_t e = hipMalloc(&s->owned_soa, total);
-    if (e != hipSuccess) {
-      free_set(s);
-      return fail(SOAX_E_OOM, "hipMalloc(%lld bytes for SoA): %s", static_cast<long long>(total),
-                  hipGetErrorString(e));
-    }
-    for (int a = 0; a < L.narrays; ++a) s->soa[a] = static_cast<char*>(s->owned_soa) + off[a];
-    e = hipMalloc(&s->owned_aos, n * L.stride);
-    if (e != hipSuccess) {
-      free_set(s);
-      return fail(SOAX_E_OOM, "hipMalloc(%lld bytes for AoS): %s",
-                  static_cast<long long>(n * L.stride), hipGetErrorString(e));
-    }
-    s->aos = static_cast<char*>(s->owned_aos);
+  s->cap = n;
+  s->owns = true;
+  if ((st = alloc_owned(L, n, &s->owned_soa, s->soa, &s->owned_aos))) {
+    free_set(s);
+    return st;
   }
+  s->aos = static_cast<char*>(s->owned_aos);
+  if ((st = finish_set(s))) {
+    free_set(s);
+    return st;
+  }
+  *out = s;
+  return SOAX_OK;
+}
+
+soax_status soax_bind_capacity(const soax_schema* schema, int64_t n, int64_t capacity,
+                               void* const* soa_ptrs, void* aos_ptr, soax_set** out) {
+  if (!out) return fail(SOAX_E_ARG, "out is NULL");
+  *out = nullptr;
+  Layout L;
+  soax_status st = parse_schema(schema, L);
+  if (st) return st;
+  if ((st = check_n(L, n)) || (st = check_n(L, capacity))) return st;
+  if (capacity < n) return fail(SOAX_E_ARG, "capacity %lld is below n = %lld",
+                                static_cast<long long>(capacity), static_cast<long long>(n));
+  if (!soa_ptrs && !aos_ptr) return fail(SOAX_E_ARG, "neither a SoA nor an AoS buffer was given");
+  if (capacity > 0 && soa_ptrs)
+    for (int a = 0; a < L.narrays; ++a)
+      if (!soa_ptrs[a]) return fail(SOAX_E_ARG, "soa_ptrs[%d] is NULL", a);
+  soax_set* s = new soax_set();
+  s->L = L;
+  s->n = n;
+  s->cap = capacity;
+  if (soa_ptrs) s->soa.assign(soa_ptrs, soa_ptrs + L.narrays);
+  s->aos = static_cast<char*>(aos_ptr);
   if ((st = finish_set(s))) {
     free_set(s);
     return st;
@@ -281,27 +336,7 @@ soax_status soax_create(const soax_schema* schema, int64_t n, soax_set** out) {
 
 soax_status soax_bind(const soax_schema* schema, int64_t n, void* const* soa_ptrs, void* aos_ptr,
                       soax_set** out) {
-  if (!out) return fail(SOAX_E_ARG, "out is NULL");
-  *out = nullptr;
-  Layout L;
-  soax_status st = parse_schema(schema, L);
-  if (st) return st;
-  if ((st = check_n(L, n))) return st;
-  if (!soa_ptrs && !aos_ptr) return fail(SOAX_E_ARG, "neither a SoA nor an AoS buffer was given");
-  if (n > 0 && soa_ptrs)
-    for (int a = 0; a < L.narrays; ++a)
-      if (!soa_ptrs[a]) return fail(SOAX_E_ARG, "soa_ptrs[%d] is NULL", a);
-  soax_set* s = new soax_set();
-  s->L = L;
-  s->n = n;
-  if (soa_ptrs) s->soa.assign(soa_ptrs, soa_ptrs + L.narrays);
-  s->aos = static_cast<char*>(aos_ptr);
-  if ((st = finish_set(s))) {
-    free_set(s);
-    return st;
-  }
-  *out = s;
-  return SOAX_OK;
+  return soax_bind_capacity(schema, n, n, soa_ptrs, aos_ptr, out);
 }
 
 void soax_destroy(soax_set* set) { free_set(set); }
@@ -428,16 +463,17 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
     a.dt = dt;
     a.abc = abc;
     a.wrap = wrap;
-    // RK2 is VALU-heavy: one particle per thread keeps more waves resident
-    int vec = set->vec ? set->vec : (integrator == SOAX_RK2_ABC ? 1 : 4);
+    // one particle per thread in workgroups of 128: the fastest shape measured
+    // on the MI355X for both the streaming Euler and the VALU-heavy RK2 step
+    int vec = set->vec ? set->vec : 1;
     if (!set->soa_vec_ok) vec = 1;
-    const int block = set->block[SOAX_SOA] ? set->block[SOAX_SOA] : 256;
+    const int block = set->block[SOAX_SOA] ? set->block[SOAX_SOA] : 128;
     for (int64_t k = 0; k < nsteps; ++k)
       HIP_TRY(launch_soa_step(integrator, L.f[fp].dtype, L.f[fv].dtype, vec, block, a, s),
               "SoA step launch");
     return SOAX_OK;
   }
-  if (!set->aos) return fail(SOAX_E_LAYOUT, "the set has no AoS copy");
+  if (!has_aos(set)) return fail(SOAX_E_LAYOUT, "the set has no AoS copy");
   AosStepArgs a{};
   a.aos = set->aos;
   a.n = set->n;
@@ -469,7 +505,7 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
 
 static soax_status xpose(soax_set* set, bool to_soa, void* stream) {
   if (!set) return fail(SOAX_E_ARG, "set is NULL");
-  if (set->soa.empty() || !set->aos) return fail(SOAX_E_LAYOUT, "the transpose needs both copies");
+  if (!has_soa(set) || !has_aos(set)) return fail(SOAX_E_LAYOUT, "the transpose needs both copies");
   if (!set->soa_vec_ok || !set->aos_base_ok)
     return fail(SOAX_E_LAYOUT, "the transpose needs 16-byte aligned buffers");
   if (set->n == 0) return SOAX_OK;
@@ -487,7 +523,7 @@ soax_status soax_get_record(const soax_set* set, int32_t layout, int64_t i, void
   const Layout& L = set->L;
   char* out = static_cast<char*>(host_record);
   if (layout == SOAX_AOS) {
-    if (!set->aos) return fail(SOAX_E_LAYOUT, "the set has no AoS copy");
+    if (!has_aos(set)) return fail(SOAX_E_LAYOUT, "the set has no AoS copy");
     HIP_TRY(hipMemcpy(out, set->aos + i * L.stride, L.stride, hipMemcpyDeviceToHost), "hipMemcpy");
     return SOAX_OK;
   }
@@ -501,6 +537,289 @@ soax_status soax_get_record(const soax_set* set, int32_t layout, int64_t i, void
                         hipMemcpyDeviceToHost),
               "hipMemcpy");
   return SOAX_OK;
+}
+
+// ----------------------------------------------------------- containers
+
+namespace {
+
+// Move an owned set into buffers for `cap` particles, keeping its n
+// particles in both copies.  Synchronises `s` before freeing the old buffers.
+soax_status grow(soax_set* set, int64_t cap, hipStream_t s) {
+  void* nsoa_block = nullptr;
+  void* naos = nullptr;
+  std::vector<void*> nsoa;
+  soax_status st = alloc_owned(set->L, cap, &nsoa_block, nsoa, &naos);
+  if (st) return st;
+  hipError_t e = hipSuccess;
+  if (set->n > 0) {
+    for (const Field& f : set->L.f)
+      for (int c = 0; c < f.dim && e == hipSuccess; ++c) {
+        const int a = f.first_array + c;
+        e = launch_copy16(nsoa[a], set->soa[a], set->n * f.es, s);
+      }
+    if (e == hipSuccess) e = launch_copy16(naos, set->aos, set->n * set->L.stride, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(nsoa_block);
+    (void)hipFree(naos);
+    return hip_fail(e, "copy into the grown buffers");
+  }
+  (void)hipFree(set->owned_soa);
+  (void)hipFree(set->owned_aos);
+  set->owned_soa = nsoa_block;
+  set->owned_aos = naos;
+  set->soa = nsoa;
+  set->aos = static_cast<char*>(naos);
+  set->cap = cap;
+  return SOAX_OK;
+}
+
+// Room for `need` particles: bound sets must already have it; owned sets
+// grow to max(need, 2 * capacity), at most 2^31-1.
+soax_status ensure_capacity(soax_set* set, int64_t need, hipStream_t s) {
+  if (need <= set->cap) return SOAX_OK;
+  if (!set->owns)
+    return fail(SOAX_E_STATE, "a bound set holds at most %lld particles (asked for %lld)",
+                static_cast<long long>(set->cap), static_cast<long long>(need));
+  return grow(set, std::max(need, std::min(2 * set->cap, kMaxParticles)), s);
+}
+
+// New size: bump the generation and refresh the transpose table once the
+// stream's earlier work (which may read the table) has finished.
+soax_status set_size(soax_set* set, int64_t n, hipStream_t s) {
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  set->n = n;
+  ++set->generation;
+  return finish_set(set);
+}
+
+// Width in bytes of the moves of one AoS record: the widest of 16, 8, 4
+// that divides the stride and the buffer's alignment.
+int record_word(const soax_set* set) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(set->aos);
+  for (int w : {16, 8, 4})
+    if (set->L.stride % w == 0 && a % w == 0) return w;
+  return 1;
+}
+
+struct DevBuf {  // stream-ordered scratch, released on the same stream
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  hipError_t alloc(size_t bytes, hipStream_t st) {
+    s = st;
+    return bytes ? hipMallocAsync(&p, bytes, st) : hipSuccess;
+  }
+  ~DevBuf() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+};
+
+}  // namespace
+
+soax_status soax_capacity(const soax_set* set, int64_t* n, int64_t* capacity) {
+  if (!set) return fail(SOAX_E_ARG, "set is NULL");
+  if (n) *n = set->n;
+  if (capacity) *capacity = set->cap;
+  return SOAX_OK;
+}
+
+soax_status soax_reserve(soax_set* set, int64_t capacity, void* stream) {
+  if (!set) return fail(SOAX_E_ARG, "set is NULL");
+  soax_status st;
+  if ((st = check_n(set->L, capacity))) return st;
+  if (capacity <= set->cap) return SOAX_OK;
+  const hipStream_t s = as_stream(stream);
+  if (!set->owns)
+    return fail(SOAX_E_STATE, "a bound set holds at most %lld particles",
+                static_cast<long long>(set->cap));
+  if ((st = grow(set, capacity, s))) return st;
+  return set_size(set, set->n, s);
+}
+
+soax_status soax_resize(soax_set* set, int64_t n, void* stream) {
+  if (!set) return fail(SOAX_E_ARG, "set is NULL");
+  soax_status st;
+  if ((st = check_n(set->L, n))) return st;
+  const hipStream_t s = as_stream(stream);
+  if ((st = ensure_capacity(set, n, s))) return st;
+  if (n > set->n) {
+    const int64_t add = n - set->n;
+    if (has_soa(set))
+      for (const Field& f : set->L.f)
+        for (int c = 0; c < f.dim; ++c)
+          HIP_TRY(launch_zero(static_cast<char*>(set->soa[f.first_array + c]) + set->n * f.es,
+                              add * f.es, s),
+                  "zero fill launch");
+    if (set->aos)
+      HIP_TRY(launch_zero(set->aos + set->n * set->L.stride, add * set->L.stride, s),
+              "zero fill launch");
+  }
+  return set_size(set, n, s);
+}
+
+soax_status soax_push_back(soax_set* set, const void* host_records, int64_t count, void* stream) {
+  if (!set) return fail(SOAX_E_ARG, "set is NULL");
+  if (count < 0) return fail(SOAX_E_ARG, "count is negative");
+  if (count > 0 && !host_records) return fail(SOAX_E_ARG, "host_records is NULL");
+  soax_status st;
+  if ((st = check_n(set->L, set->n + count))) return st;
+  if (has_soa(set) && !set->owns && !set->soa_vec_ok)
+    return fail(SOAX_E_LAYOUT, "push_back needs 16-byte aligned SoA arrays");
+  const hipStream_t s = as_stream(stream);
+  if ((st = ensure_capacity(set, set->n + count, s))) return st;
+  if (count == 0) return SOAX_OK;
+  const Layout& L = set->L;
+  const int64_t n0 = set->n;
+  const int64_t bytes = count * L.stride;
+  {
+    DevBuf stage, table;
+    HIP_TRY(stage.alloc(bytes, s), "hipMallocAsync(staging)");
+    HIP_TRY(hipMemcpyAsync(stage.p, host_records, bytes, hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync(records)");
+    XposeArgs t = set->xpose_host;  // same fields; the appended range only
+    if (has_soa(set)) {
+      t.aos = static_cast<char*>(stage.p);
+      t.n = count;
+      t.stride = static_cast<int32_t>(L.stride);
+      t.narrays = L.narrays;
+      t.aligned = 1;
+      for (const Field& f : L.f) {
+        if (f.off % f.es || L.stride % f.es) t.aligned = 0;
+        for (int c = 0; c < f.dim; ++c) {
+          const int a = f.first_array + c;
+          t.soa[a] = static_cast<char*>(set->soa[a]) + n0 * f.es;
+          t.off[a] = static_cast<int32_t>(f.off + c * f.es);
+          t.es[a] = f.es;
+        }
+      }
+      HIP_TRY(table.alloc(sizeof(XposeArgs), s), "hipMallocAsync(table)");
+      HIP_TRY(hipMemcpyAsync(table.p, &t, sizeof(XposeArgs), hipMemcpyHostToDevice, s),
+              "hipMemcpyAsync(table)");
+      HIP_TRY(launch_xpose(true, t, static_cast<const XposeArgs*>(table.p), s), "transpose launch");
+    }
+    if (set->aos)
+      HIP_TRY(hipMemcpyAsync(set->aos + n0 * L.stride, stage.p, bytes, hipMemcpyDeviceToDevice, s),
+              "hipMemcpyAsync(records)");
+    // the host records and the host table must outlive the copies
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  }
+  return set_size(set, n0 + count, s);
+}
+
+soax_status soax_rebind(soax_set* set, int64_t capacity, void* const* soa_ptrs, void* aos_ptr,
+                        void* stream) {
+  if (!set) return fail(SOAX_E_ARG, "set is NULL");
+  if (set->owns) return fail(SOAX_E_STATE, "the set owns its buffers (use soax_reserve)");
+  soax_status st;
+  if ((st = check_n(set->L, capacity))) return st;
+  if (capacity < set->n)
+    return fail(SOAX_E_ARG, "capacity %lld is below n = %lld", static_cast<long long>(capacity),
+                static_cast<long long>(set->n));
+  if (has_soa(set) != (soa_ptrs != nullptr) || has_aos(set) != (aos_ptr != nullptr))
+    return fail(SOAX_E_LAYOUT, "the new buffers must give the same copies as the old ones");
+  if (capacity > 0 && soa_ptrs)
+    for (int a = 0; a < set->L.narrays; ++a)
+      if (!soa_ptrs[a]) return fail(SOAX_E_ARG, "soa_ptrs[%d] is NULL", a);
+  const hipStream_t s = as_stream(stream);
+  auto move = [&](void* dst, const void* src, int64_t bytes) {
+    if (bytes == 0) return hipSuccess;
+    if (aligned16(dst) && aligned16(src)) return launch_copy16(dst, src, bytes, s);
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+  };
+  if (set->n > 0) {
+    if (soa_ptrs)
+      for (const Field& f : set->L.f)
+        for (int c = 0; c < f.dim; ++c) {
+          const int a = f.first_array + c;
+          HIP_TRY(move(soa_ptrs[a], set->soa[a], set->n * f.es), "copy into the new buffers");
+        }
+    if (aos_ptr)
+      HIP_TRY(move(aos_ptr, set->aos, set->n * set->L.stride), "copy into the new buffers");
+  }
+  if (soa_ptrs) set->soa.assign(soa_ptrs, soa_ptrs + set->L.narrays);
+  set->aos = static_cast<char*>(aos_ptr);
+  set->cap = capacity;
+  return set_size(set, set->n, s);
+}
+
+soax_status soax_set_record(soax_set* set, int64_t i, const void* host_record) {
+  if (!set || !host_record) return fail(SOAX_E_ARG, "set or host_record is NULL");
+  if (i < 0 || i >= set->n) return fail(SOAX_E_ARG, "record %lld out of range", static_cast<long long>(i));
+  const Layout& L = set->L;
+  const char* in = static_cast<const char*>(host_record);
+  if (set->aos)
+    HIP_TRY(hipMemcpy(set->aos + i * L.stride, in, L.stride, hipMemcpyHostToDevice), "hipMemcpy");
+  if (has_soa(set))
+    for (const Field& f : L.f)
+      for (int c = 0; c < f.dim; ++c)
+        HIP_TRY(hipMemcpy(static_cast<char*>(set->soa[f.first_array + c]) + i * f.es,
+                          in + f.off + c * f.es, f.es, hipMemcpyHostToDevice),
+                "hipMemcpy");
+  return SOAX_OK;
+}
+
+soax_status soax_remove_flagged(soax_set* set, const uint8_t* flags, int64_t* new_n, void* stream) {
+  if (!set || !new_n) return fail(SOAX_E_ARG, "set or new_n is NULL");
+  const int64_t n = set->n;
+  if (n > 0 && !flags) return fail(SOAX_E_ARG, "flags is NULL");
+  *new_n = n;
+  if (n == 0) return SOAX_OK;
+  const hipStream_t s = as_stream(stream);
+  const int64_t tiles = container_tiles(n);
+  std::vector<int32_t> counts(tiles);
+  DevBuf dcounts;
+  HIP_TRY(dcounts.alloc(tiles * sizeof(int32_t), s), "hipMallocAsync(counts)");
+  int32_t* dc = static_cast<int32_t*>(dcounts.p);
+  HIP_TRY(launch_count_flags(flags, n, dc, s), "flag count launch");
+  HIP_TRY(hipMemcpyAsync(counts.data(), dc, tiles * sizeof(int32_t), hipMemcpyDeviceToHost, s),
+          "hipMemcpyAsync(counts)");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  int64_t m = 0;
+  for (int32_t c : counts) m += c;
+  const int64_t n_new = n - m;
+  const int64_t moves_max = std::min(m, n_new);
+  if (moves_max > 0) {
+    // holes_before[b]: flagged in tiles < b; movers_after[b]: unflagged in tiles > b
+    const int64_t T = container_tile_size();
+    std::vector<int64_t> tab(2 * tiles);
+    int64_t acc = 0;
+    for (int64_t b = 0; b < tiles; ++b) {
+      tab[b] = acc;
+      acc += counts[b];
+    }
+    acc = 0;
+    for (int64_t b = tiles - 1; b >= 0; --b) {
+      tab[tiles + b] = acc;
+      acc += std::min(T, n - b * T) - counts[b];
+    }
+    DevBuf dtab, dlists;
+    HIP_TRY(dtab.alloc(tab.size() * sizeof(int64_t), s), "hipMallocAsync(offsets)");
+    HIP_TRY(dlists.alloc((2 * moves_max + 1) * sizeof(int64_t), s), "hipMallocAsync(lists)");
+    int64_t* dt = static_cast<int64_t*>(dtab.p);
+    int64_t* hole_at = static_cast<int64_t*>(dlists.p);
+    int64_t* mover_at = hole_at + moves_max;
+    int64_t* nmoves = mover_at + moves_max;
+    HIP_TRY(hipMemcpyAsync(dt, tab.data(), tab.size() * sizeof(int64_t), hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync(offsets)");
+    HIP_TRY(launch_rank_flags(flags, n, n_new, dt, dt + tiles, hole_at, mover_at, nmoves, s),
+            "rank launch");
+    if (has_soa(set))
+      for (const Field& f : set->L.f)
+        for (int c = 0; c < f.dim; ++c)
+          HIP_TRY(launch_move(set->soa[f.first_array + c], f.es, f.es, hole_at, mover_at, nmoves,
+                              moves_max, s),
+                  "move launch");
+    if (set->aos)
+      HIP_TRY(launch_move(set->aos, set->L.stride, record_word(set), hole_at, mover_at, nmoves,
+                          moves_max, s),
+              "move launch");
+    // the host offset table must outlive its copy
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  }
+  *new_n = n_new;
+  return set_size(set, n_new, s);
 }
 
 // ------------------------------------------------------------- adjoints
@@ -701,6 +1020,15 @@ soax_status upload_params(soax_batch* b, const double* dt, const double* abc, hi
   return SOAX_OK;
 }
 
+// A set resized or regrown since the batch was made invalidates the batch's
+// tables (sizes, pointers, tiles, captured graphs).
+soax_status check_generations(const soax_batch* b) {
+  for (size_t i = 0; i < b->sets.size(); ++i)
+    if (b->sets[i]->generation != b->generations[i])
+      return fail(SOAX_E_STATE, "set %zu changed size since the batch was created", i);
+  return SOAX_OK;
+}
+
 soax_status per_set_step(soax_batch* b, const double* dt, const double* abc, hipStream_t s) {
   for (size_t i = 0; i < b->sets.size(); ++i) {
     soax_set* set = b->sets[i];
@@ -715,7 +1043,7 @@ soax_status per_set_step(soax_batch* b, const double* dt, const double* abc, hip
     a.dt = dt[i];
     a.abc = AbcParams{abc[3 * i], abc[3 * i + 1], abc[3 * i + 2]};
     a.wrap = 1;
-    HIP_TRY(launch_soa_step(kRk2Abc, kF64, b->vel_t, 1, 256, a, s), "per-set step launch");
+    HIP_TRY(launch_soa_step(kRk2Abc, kF64, b->vel_t, 1, 128, a, s), "per-set step launch");
   }
   return SOAX_OK;
 }
@@ -774,6 +1102,7 @@ soax_status soax_batch_create(soax_set* const* sets, int32_t nsets, soax_batch**
   }
   soax_batch* b = new soax_batch();
   b->sets.assign(sets, sets + nsets);
+  for (int i = 0; i < nsets; ++i) b->generations.push_back(sets[i]->generation);
   b->vel_t = vel_t;
   b->total = total;
   int dev = 0;
@@ -855,6 +1184,8 @@ soax_status soax_batch_step(soax_batch* b, const double* dt, const double* abc, 
   if (!dt || !abc) return fail(SOAX_E_ARG, "dt or abc is NULL");
   if (nsteps < 0) return fail(SOAX_E_ARG, "nsteps is negative");
   if (mode < 0 || mode > 2) return fail(SOAX_E_ARG, "mode must be 0, 1 or 2");
+  soax_status st0 = check_generations(b);
+  if (st0) return st0;
   for (size_t i = 0; i < b->sets.size(); ++i) {
     if (!is_finite(dt[i])) return fail(SOAX_E_ARG, "dt[%zu] is not finite", i);
     for (int j = 0; j < 3; ++j)
@@ -964,6 +1295,8 @@ soax_status snapshot(soax_batch* b, Snapshot& snap, bool restore) {
 
 extern "C" soax_status soax_batch_tune(soax_batch* b, const char* cache_path) {
   if (!b) return fail(SOAX_E_ARG, "batch is NULL");
+  soax_status st0 = check_generations(b);
+  if (st0) return st0;
   char keybuf[256];
   snprintf(keybuf, sizeof keybuf, "%s|batch_rk2|vel%d|sets=%zu|n=%lld", b->arch.c_str(), b->vel_t,
            b->sets.size(), static_cast<long long>(b->total));

@@ -61,31 +61,61 @@ class Schema:
 
 
 class ParticleSet:
-    """n particles of a schema, both layouts resident on the current GPU."""
+    """n particles of a schema, both layouts resident on the current GPU.
 
-    def __init__(self, fields, n, packed=False, soa=True, aos=True, pad=64):
+    The buffers hold `capacity` >= n particles; resize and push_back grow
+    them (to at least twice the capacity) through the library, which copies
+    the particles into the new buffers."""
+
+    def __init__(self, fields, n, packed=False, soa=True, aos=True, pad=64, capacity=None):
         if not torch.cuda.is_available():
             raise RuntimeError("ParticleSet needs a GPU")
         self.schema = Schema(fields, packed)
         self.n = int(n)
+        self.pad = int(pad)
         self.offsets, self.stride, self.soa_bytes = self.schema.layout()
-        dev = torch.device("cuda", torch.cuda.current_device())
-        ld = max(pad, -(-self.n // pad) * pad)
-        self.soa = None
-        if soa:
-            self._soa_store = [torch.empty(ld, dtype=TORCH_DTYPE[t], device=dev)
-                               for _, _, t in self.schema.arrays()]
-            self.soa = [b[: self.n] for b in self._soa_store]
-        self.aos = torch.zeros(max(self.n * self.stride, 16), dtype=torch.uint8,
-                               device=dev) if aos else None
-        ptrs = None
-        if soa:
-            ptrs = (ctypes.c_void_p * len(self.soa))(*[t.data_ptr() for t in self.soa])
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._has_soa, self._has_aos = bool(soa), bool(aos)
+        cap = max(self.n, int(capacity or 0))
+        self._alloc(cap)
         h = ctypes.c_void_p()
-        check(lib().soax_bind(self.schema.ref, self.n, ptrs,
-                              ctypes.c_void_p(self.aos.data_ptr()) if aos else None,
-                              ctypes.byref(h)), "soax_bind")
+        check(lib().soax_bind_capacity(self.schema.ref, self.n, self.capacity, self._soa_ptrs(),
+                                       self._aos_ptr(), ctypes.byref(h)), "soax_bind_capacity")
         self.handle = h
+        self._views()
+
+    # --------------------------------------------------------------- storage
+    def _alloc(self, cap):
+        ld = max(self.pad, -(-cap // self.pad) * self.pad)
+        self.capacity = ld  # the buffers' whole length is usable
+        self._soa_store = [torch.empty(ld, dtype=TORCH_DTYPE[t], device=self.device)
+                           for _, _, t in self.schema.arrays()] if self._has_soa else None
+        self._aos_store = torch.zeros(max(ld * self.stride, 16), dtype=torch.uint8,
+                                      device=self.device) if self._has_aos else None
+
+    def _soa_ptrs(self):
+        if not self._has_soa:
+            return None
+        return (ctypes.c_void_p * len(self._soa_store))(*[t.data_ptr() for t in self._soa_store])
+
+    def _aos_ptr(self):
+        return ctypes.c_void_p(self._aos_store.data_ptr()) if self._has_aos else None
+
+    def _views(self):
+        n = ctypes.c_int64()
+        check(lib().soax_capacity(self.handle, ctypes.byref(n), None), "soax_capacity")
+        self.n = n.value
+        self.soa = [b[: self.n] for b in self._soa_store] if self._has_soa else None
+        self.aos = self._aos_store if self._has_aos else None
+
+    def _ensure(self, need):
+        if need <= self.capacity:
+            return
+        old = (self._soa_store, self._aos_store)
+        self._alloc(max(need, 2 * self.capacity))
+        check(lib().soax_rebind(self.handle, self.capacity, self._soa_ptrs(), self._aos_ptr(),
+                                current_stream()), "soax_rebind")
+        del old  # the library has copied the particles and synchronised
 
     # -------------------------------------------------------------- lifetime
     def close(self):
@@ -98,6 +128,50 @@ class ParticleSet:
             self.close()
         except Exception:
             pass
+
+    # ------------------------------------------------------------ containers
+    def resize(self, n):
+        """New size; particles beyond the old size are zero bytes."""
+        self._ensure(int(n))
+        check(lib().soax_resize(self.handle, int(n), current_stream()), "soax_resize")
+        self._views()
+
+    def reserve(self, capacity):
+        self._ensure(int(capacity))
+
+    def push_back(self, records):
+        """Append AoS-form records (bytes or a uint8 array of count * stride)."""
+        buf = np.ascontiguousarray(np.frombuffer(bytes(records), np.uint8)
+                                   if isinstance(records, (bytes, bytearray)) else records,
+                                   dtype=np.uint8)
+        if buf.size % self.stride:
+            raise ValueError(f"{buf.size} bytes is not a whole number of {self.stride}-byte records")
+        count = buf.size // self.stride
+        self._ensure(self.n + count)
+        check(lib().soax_push_back(self.handle, buf.ctypes.data_as(ctypes.c_void_p), count,
+                                   current_stream()), "soax_push_back")
+        self._views()
+
+    def set_record(self, i, record):
+        buf = np.ascontiguousarray(np.frombuffer(bytes(record), np.uint8))
+        if buf.size != self.stride:
+            raise ValueError(f"a record is {self.stride} bytes")
+        check(lib().soax_set_record(self.handle, int(i), buf.ctypes.data_as(ctypes.c_void_p)),
+              "soax_set_record")
+
+    def remove_flagged(self, flags):
+        """Remove particles whose flag (a uint8 device tensor of n) is nonzero by
+        overwriting them with the last particle; returns the new size."""
+        if flags.dtype not in (torch.uint8, torch.bool) or not flags.is_cuda:
+            raise TypeError("flags must be a uint8 or bool device tensor")
+        if flags.numel() < self.n or not flags.is_contiguous():
+            raise ValueError("flags must be a contiguous tensor of n elements")
+        new_n = ctypes.c_int64()
+        check(lib().soax_remove_flagged(self.handle, ctypes.c_void_p(flags.data_ptr()),
+                                        ctypes.byref(new_n), current_stream()),
+              "soax_remove_flagged")
+        self._views()
+        return new_n.value
 
     # ------------------------------------------------------------ operations
     def fill(self, seed=0, vel_mode=0, abc=None):
@@ -140,6 +214,7 @@ class ParticleSet:
         return [t.cpu().numpy() for t in self.soa]
 
     def upload_aos(self, buf):
+        assert self.aos is not None
         self.aos[: self.n * self.stride].copy_(torch.from_numpy(np.ascontiguousarray(buf)))
 
     def download_aos(self):

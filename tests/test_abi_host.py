@@ -34,7 +34,9 @@ def test_header_declarations_match_binding_signatures():
              "soax_soa_to_aos", "soax_get_record", "soax_rk2_forward_ckpt", "soax_adjoint",
              "soax_sqdist_loss", "soax_batch_create", "soax_batch_destroy", "soax_batch_step",
              "soax_batch_config", "soax_batch_get_config", "soax_batch_tune", "soax_copy",
-             "soax_strerror", "soax_last_error"}
+             "soax_strerror", "soax_last_error", "soax_bind_capacity", "soax_capacity",
+             "soax_reserve", "soax_resize", "soax_push_back", "soax_rebind", "soax_set_record",
+             "soax_remove_flagged"}
     assert declared == bound
 
 
@@ -182,3 +184,49 @@ def test_strerror(L):
     assert L.soax_strerror(0) == b"ok"
     assert L.soax_strerror(-4) == b"layout unavailable"
     assert L.soax_strerror(-99) == b"unknown status"
+
+
+E_STATE = -7
+
+
+def test_container_validation(L, soa_only_set):
+    """Container calls on a bound set reject what they cannot do before any
+    device call: growing past the bound capacity, bad sizes, null buffers."""
+    h = soa_only_set(si.BASE_FIELDS)  # 1000 particles, capacity 1000, no AoS copy
+    n, cap = ctypes.c_int64(), ctypes.c_int64()
+    assert L.soax_capacity(h, ctypes.byref(n), ctypes.byref(cap)) == 0
+    assert (n.value, cap.value) == (1000, 1000)
+    assert L.soax_capacity(None, None, None) == E_ARG
+    assert L.soax_resize(h, -1, None) == E_ARG
+    assert L.soax_resize(h, 2 ** 31, None) == E_RANGE
+    assert L.soax_resize(h, 1001, None) == E_STATE        # bound sets do not grow
+    assert b"bound" in L.soax_last_error()
+    assert L.soax_reserve(h, 5000, None) == E_STATE
+    assert L.soax_reserve(h, 10, None) == 0               # never shrinks: no-op
+    rec = (ctypes.c_uint8 * 48)()
+    assert L.soax_push_back(h, rec, -1, None) == E_ARG
+    assert L.soax_push_back(h, None, 1, None) == E_ARG
+    assert L.soax_push_back(h, rec, 1, None) == E_STATE
+    assert L.soax_set_record(h, 1000, rec) == E_ARG
+    new_n = ctypes.c_int64()
+    assert L.soax_remove_flagged(h, None, ctypes.byref(new_n), None) == E_ARG
+    assert L.soax_remove_flagged(h, None, None, None) == E_ARG
+    assert L.soax_rebind(h, 999, None, None, None) == E_ARG    # below n
+    assert L.soax_rebind(h, 2000, None, None, None) == E_LAYOUT  # the SoA copy is missing
+    ptrs = (ctypes.c_void_p * 7)(*[0x200000 * (a + 1) for a in range(7)])
+    assert L.soax_rebind(h, 2000, ptrs, ctypes.c_void_p(0x9000000), None) == E_LAYOUT  # AoS added
+    assert L.soax_capacity(h, ctypes.byref(n), ctypes.byref(cap)) == 0
+    assert (n.value, cap.value) == (1000, 1000)            # nothing changed
+
+
+def test_bind_capacity_validation(L):
+    sch, keep = _lib.make_schema(si.BASE_FIELDS)
+    ptrs = (ctypes.c_void_p * 7)(*[0x100000 * (a + 1) for a in range(7)])
+    h = ctypes.c_void_p()
+    assert L.soax_bind_capacity(ctypes.byref(sch), 10, 5, ptrs, None, ctypes.byref(h)) == E_ARG
+    assert L.soax_bind_capacity(ctypes.byref(sch), 10, 2 ** 31, ptrs, None, ctypes.byref(h)) == E_RANGE
+    assert L.soax_bind_capacity(ctypes.byref(sch), 10, 64, ptrs, None, ctypes.byref(h)) == 0
+    n, cap = ctypes.c_int64(), ctypes.c_int64()
+    assert L.soax_capacity(h, ctypes.byref(n), ctypes.byref(cap)) == 0
+    assert (n.value, cap.value) == (10, 64)
+    L.soax_destroy(h)
