@@ -235,6 +235,66 @@ soax_status soax_set_record(soax_set* set, int64_t i, const void* host_record);
  */
 soax_status soax_remove_flagged(soax_set* set, const uint8_t* flags, int64_t* new_n, void* stream);
 
+/* ----------------------------------------------------------- expressions */
+
+/*
+ * Fused element-wise expressions over whole arrays (the array access of
+ * Section 4.1, e.g. posArr(0) = velArr(1) - velArr(2), and its evaluation as
+ * one loop by expression templates, Section 4.2).  A program is a postfix
+ * list of ops on a value stack:
+ *   SOAX_OP_ARRAY  push element i of array `arg`;   SOAX_OP_CONST  push `value`;
+ *   SOAX_OP_ADD, _SUB, _MUL, _DIV  pop b, pop a, push a op b;
+ *   SOAX_OP_MIN, _MAX  pop b, pop a, push (a < b ? a : b) / (a > b ? a : b);
+ *   SOAX_OP_NEG, _ABS, _SQRT  replace the top value.
+ * Every value is a double: array elements are converted to double (exact for
+ * every type but i64 beyond 2^53, which rounds to nearest), each operation is
+ * one IEEE double operation rounded to nearest (none is fused into an fma),
+ * and the result is rounded once to the destination type (f32 or f64).  At
+ * most 64 ops, 8 distinct arrays and 32 constants; the stack must end with
+ * one value.  The kernel for a program's shape (its ops and element types)
+ * is generated and compiled with hipRTC on the first call on a device and
+ * cached for the life of the process; constants and pointers are arguments.
+ * The destination may also be read by the program (each element is read
+ * before it is written).
+ */
+typedef struct {
+  int32_t op;
+  int32_t arg;  /* SOAX_OP_ARRAY: array index */
+  double value; /* SOAX_OP_CONST: the constant */
+} soax_expr_op;
+#define SOAX_OP_ARRAY 0
+#define SOAX_OP_CONST 1
+#define SOAX_OP_ADD 2
+#define SOAX_OP_SUB 3
+#define SOAX_OP_MUL 4
+#define SOAX_OP_DIV 5
+#define SOAX_OP_NEG 6
+#define SOAX_OP_ABS 7
+#define SOAX_OP_SQRT 8
+#define SOAX_OP_MIN 9
+#define SOAX_OP_MAX 10
+
+/* SoA array dst_array of a set (f32 or f64) = program over the set's SoA
+ * arrays (arg = array index, numbered as in soax_bind), for its n particles.
+ * Errors: ARG (bad program or index), SCHEMA (integer destination), LAYOUT
+ * (no SoA copy), HIP (compilation or launch; the message has the compiler
+ * log). */
+soax_status soax_eval(soax_set* set, int32_t dst_array, const soax_expr_op* prog, int32_t nops,
+                      void* stream);
+
+/* The same over plain device arrays of n elements: src[j] has type
+ * src_dtypes[j] (a soax_dtype), arg = j; dst has type dst_dtype (f32 or
+ * f64).  Pointers must be aligned to their element size. */
+soax_status soax_eval_ptrs(int64_t n, void* dst, int32_t dst_dtype, const void* const* src,
+                           const int32_t* src_dtypes, int32_t nsrc, const soax_expr_op* prog,
+                           int32_t nops, void* stream);
+
+/* Host only: the HIP source of the kernel a program compiles to, as a
+ * NUL-terminated string in buf (size bytes).  Errors: ARG (bad program or
+ * buffer too small), SCHEMA. */
+soax_status soax_expr_source(const soax_expr_op* prog, int32_t nops, int32_t dst_dtype,
+                             const int32_t* src_dtypes, int32_t nsrc, char* buf, int64_t size);
+
 /* ------------------------------------------------ differentiable advection */
 
 /*

@@ -170,6 +170,54 @@ def remove_flagged(schema, arrays, flags):
     return [a[:m] for a in arrays], m
 
 
+# Postfix op codes of the fused array expressions.
+OP_ARRAY, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_NEG, OP_ABS, OP_SQRT, OP_MIN, OP_MAX = range(11)
+
+
+def eval_program(arrays, prog, dst_dtype=np.float64):
+    """A whole-array expression (the array access of Section 4.1, e.g.
+    posArr(0) = velArr(1) - velArr(2)) applied element by element: the
+    postfix program ``prog`` of (op, arg, value) triples is evaluated on a
+    stack of float64 arrays in program order, one IEEE double operation per
+    step (array elements converted to double first), and the result is
+    rounded once to ``dst_dtype``.  MIN/MAX are (a < b ? a : b) and
+    (a > b ? a : b)."""
+    stack = []
+    for op, arg, value in prog:
+        if op == OP_ARRAY:
+            stack.append(np.asarray(arrays[arg]).astype(np.float64))
+        elif op == OP_CONST:
+            n = len(arrays[0]) if arrays else 1
+            stack.append(np.full(n, float(value), dtype=np.float64))
+        elif op in (OP_NEG, OP_ABS, OP_SQRT):
+            x = stack.pop()
+            with np.errstate(invalid="ignore"):
+                stack.append(-x if op == OP_NEG else np.abs(x) if op == OP_ABS else np.sqrt(x))
+        else:
+            b = stack.pop()
+            a = stack.pop()
+            with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+                if op == OP_ADD:
+                    r = a + b
+                elif op == OP_SUB:
+                    r = a - b
+                elif op == OP_MUL:
+                    r = a * b
+                elif op == OP_DIV:
+                    r = a / b
+                elif op == OP_MIN:
+                    r = np.where(a < b, a, b)
+                elif op == OP_MAX:
+                    r = np.where(a > b, a, b)
+                else:
+                    raise ValueError(f"unknown op {op}")
+            stack.append(r)
+    if len(stack) != 1:
+        raise ValueError("the program must leave exactly one value")
+    with np.errstate(over="ignore"):
+        return stack[0].astype(dst_dtype)
+
+
 def field(abc, x):
     """u(x) for one point x (3,)."""
     a, ap = _abc(abc)

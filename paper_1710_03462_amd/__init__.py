@@ -8,9 +8,11 @@ from ._lib import (AOS, AOS_NAIVE, EULER, EULER_ACC, RK2_ABC, SOA, SoaxError, ch
                    exported_names, lib)
 from .autograd import RK2Advect, adjoint, forward_ckpt, rk2_advect, sqdist_loss
 from .batch import GRAPH, PER_SET, PERSISTENT, Batch
+from .expr import Expr, array, evaluate, maximum, minimum, sqrt
 from .particles import ParticleSet, Schema, copy, current_stream, params
 
 __all__ = ["AOS", "AOS_NAIVE", "EULER", "EULER_ACC", "RK2_ABC", "SOA", "SoaxError", "check",
            "exported_names", "lib", "RK2Advect", "adjoint", "forward_ckpt", "rk2_advect",
            "sqdist_loss", "GRAPH", "PER_SET", "PERSISTENT", "Batch", "ParticleSet", "Schema",
-           "copy", "current_stream", "params"]
+           "copy", "current_stream", "params", "Expr", "array", "evaluate", "maximum", "minimum",
+           "sqrt"]

@@ -94,6 +94,9 @@ def lib():
         "soax_rebind": [vp, i64, vp, vp, vp],
         "soax_set_record": [vp, i64, vp],
         "soax_remove_flagged": [vp, vp, vp, vp],
+        "soax_eval": [vp, i32, vp, i32, vp],
+        "soax_eval_ptrs": [i64, vp, i32, vp, vp, i32, vp, i32, vp],
+        "soax_expr_source": [vp, i32, i32, vp, i32, vp, i64],
         "soax_copy": [vp, vp, i64, vp],
         "soax_strerror": [i32],
         "soax_last_error": [],

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsoax.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["soax_host.cpp", "k_step.hip", "k_adjoint.hip", "k_batch.hip", "k_container.hip"]
+SOURCES = ["soax_host.cpp", "expr.cpp", "k_step.hip", "k_adjoint.hip", "k_batch.hip",
+           "k_container.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
@@ -44,7 +45,7 @@ def build(verbose=False, jobs=4):
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lhiprtc"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

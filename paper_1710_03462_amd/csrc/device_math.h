@@ -61,12 +61,13 @@ __device__ __forceinline__ Trig3 trig3_shift(const Trig3& t, double x, double y,
 
 static_assert(kShiftLimit == trig::kShiftMax, "small_steps must match the shift bound");
 
-// u = (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x)
+// u = (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x), each
+// component one product and one fused multiply-add
 __device__ __forceinline__ void field_of(const Abc& p, const Trig3& t, double& u0, double& u1,
                                          double& u2) {
-  u0 = p.A * t.sz + p.C * t.cy;
-  u1 = p.B * t.sx + p.A * t.cz;
-  u2 = p.C * t.sy + p.B * t.cx;
+  u0 = fma(p.A, t.sz, p.C * t.cy);
+  u1 = fma(p.B, t.sx, p.A * t.cz);
+  u2 = fma(p.C, t.sy, p.B * t.cx);
 }
 
 __device__ __forceinline__ void abc_field(const Abc& p, double x, double y, double z, double& u0,

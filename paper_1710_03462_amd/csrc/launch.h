@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace soax {
 
 struct Abc;
@@ -32,7 +34,7 @@ struct AbcParams {
 
 // Largest displacement per coordinate for which a step's midpoint and end
 // point sines come from its start point by angle addition without a check.
-constexpr double kShiftLimit = 0.125;
+constexpr double kShiftLimit = 1.0 / 64;
 
 // True when every displacement of a midpoint step, (dt/2) u and dt u, is at
 // most kShiftLimit in each coordinate, since |u_i| <= |A| + |B| + |C|.
@@ -194,6 +196,43 @@ hipError_t launch_move(void* arr, int64_t stride, int word, const int64_t* hole_
                        hipStream_t s);
 // p[0, bytes) = 0.
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
+
+// ------------------------------------------------------------ expressions
+
+// Fused element-wise expression: dst[i] = program(src...[i]), i < n.  Op codes
+// have the values of the soax_expr_op codes.
+enum ExprOpCode : int32_t {
+  kOpArray = 0, kOpConst = 1, kOpAdd = 2, kOpSub = 3, kOpMul = 4, kOpDiv = 5,
+  kOpNeg = 6, kOpAbs = 7, kOpSqrt = 8, kOpMin = 9, kOpMax = 10
+};
+constexpr int kExprMaxOps = 64;
+constexpr int kExprMaxSrc = 8;
+constexpr int kExprMaxConst = 32;
+
+struct ExprOp {
+  int32_t op, arg;
+  double value;
+};
+
+// A validated program: every kOpArray arg < nsrc, at most kExprMaxConst
+// constants, the stack never underflows and ends with one value.
+struct ExprPlan {
+  int nops;
+  ExprOp ops[kExprMaxOps];
+  int nsrc;
+  const void* src[kExprMaxSrc];
+  int32_t src_t[kExprMaxSrc];
+  void* dst;
+  int32_t dst_t;
+  int64_t n;
+  bool stream;  // nontemporal loads and stores
+};
+
+// Compiles the program's kernel on first use (hipRTC, cached per program
+// shape and device) and launches it; a compiler message goes to *log.
+hipError_t launch_expr(const ExprPlan& p, hipStream_t s, std::string* log);
+// The generated source (for inspection and tests).
+std::string expr_source(const ExprPlan& p);
 
 // -------------------------------------------------------------- batching
 

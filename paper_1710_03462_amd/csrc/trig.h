@@ -15,12 +15,12 @@
 // device library's sincos.
 //
 // sincos_shift(x, sin x, cos x, d): both functions of x + d for a small shift
-// |d| <= 1/8, by the angle-addition formulas with sin d and cos d - 1 from
-// their Taylor series (truncated after d^9 and d^10; omitted terms below
-// 3e-17 relative).  A time step moves a particle by dt*u, far less than 1/8,
-// so the midpoint and end-point values of a step come from the start-point
-// values without a second reduction; larger shifts fall back to
-// sincos_fast(x + d).  The shift uses the exact sum x + d, which differs from
+// |d| <= 1/64, by the angle-addition formulas with sin d and cos d - 1 from
+// their Taylor series (truncated after d^5 and d^6; omitted terms below
+// 5e-17 absolute).  A time step moves a particle by dt*u, far less than 1/64
+// for the step sizes of interest, so the midpoint and end-point values of a
+// step come from the start-point values without a second reduction; larger
+// shifts fall back to sincos_fast(x + d).  The shift uses the exact sum x + d, which differs from
 // the rounded sum by at most half an ulp of x.
 //
 // Every result is within about one ulp of the exact value (checked against
@@ -37,7 +37,7 @@ constexpr double kPio2Mid = 0x1.0b4611a600000p-34;
 constexpr double kPio2Lo = 0x1.3198a2e037073p-69;
 constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
 constexpr double kFastMax = 0x1p19;
-constexpr double kShiftMax = 0.125;
+constexpr double kShiftMax = 1.0 / 64;
 
 // 1/n! rounded once: n! is exact in a double for n <= 18.
 constexpr double inv_fact(int n) {
@@ -113,10 +113,10 @@ __host__ __device__ __forceinline__ void sincos_fast(double x, double* s, double
   *c = ((q + 1) & 2) ? -b : b;
 }
 
-// sin d = d + d^3 (T1 + w (T2 + w (T3 + w T4)))
-constexpr double T1 = -inv_fact(3), T2 = inv_fact(5), T3 = -inv_fact(7), T4 = inv_fact(9);
-// cos d - 1 = w (-1/2 + w (U1 + w (U2 + w (U3 + w U4))))
-constexpr double U1 = inv_fact(4), U2 = -inv_fact(6), U3 = inv_fact(8), U4 = -inv_fact(10);
+// sin d = d + d^3 (T1 + w T2)
+constexpr double T1 = -inv_fact(3), T2 = inv_fact(5);
+// cos d - 1 = w (-1/2 + w (U1 + w U2))
+constexpr double U1 = inv_fact(4), U2 = -inv_fact(6);
 
 // CHECKED = false: the caller guarantees |d| <= kShiftMax.
 template <bool CHECKED = true>
@@ -129,14 +129,8 @@ __host__ __device__ __forceinline__ void sincos_shift(double x, double sx, doubl
     }
   }
   const double w = d * d;
-  double p = w * T4 + T3;
-  p = fma_k(w, p, T2);
-  p = fma_k(w, p, T1);
-  const double sd = fma(d * w, p, d);
-  double q = w * U4 + U3;
-  q = fma_k(w, q, U2);
-  q = fma_k(w, q, U1);
-  const double cm1 = w * fma(w, q, -0.5);
+  const double sd = fma(d * w, w * T2 + T1, d);
+  const double cm1 = w * fma(w, w * U2 + U1, -0.5);
   // sin(x+d) = sin x + (sin x (cos d - 1) + cos x sin d), likewise for cos
   *s = fma(cx, sd, fma(sx, cm1, sx));
   *c = fma(-sx, sd, fma(cx, cm1, cx));

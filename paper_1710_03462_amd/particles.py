@@ -173,6 +173,27 @@ class ParticleSet:
         self._views()
         return new_n.value
 
+    # ----------------------------------------------------------- expressions
+    def arr(self, name, comp=0):
+        """Array `comp` of property `name` as an expression leaf."""
+        from .expr import ARRAY, Expr
+        return Expr([(ARRAY, ("soa", id(self), self.schema.array_index(name, comp)), 0.0)])
+
+    def assign(self, dst, expr):
+        """SoA array dst = (name, comp) or an array index, set to the fused
+        expression over this set's arrays, for all n particles."""
+        from .expr import as_expr
+        expr = as_expr(expr)
+        d = dst if isinstance(dst, int) else self.schema.array_index(*dst)
+
+        def index_of(key):
+            if not (isinstance(key, tuple) and key[:2] == ("soa", id(self))):
+                raise ValueError("the expression reads arrays of another set")
+            return key[2]
+
+        prog = expr.program(index_of)
+        check(lib().soax_eval(self.handle, d, prog, len(prog), current_stream()), "soax_eval")
+
     # ------------------------------------------------------------ operations
     def fill(self, seed=0, vel_mode=0, abc=None):
         p = params(abc)

@@ -51,7 +51,8 @@ int main(int argc, char** argv) {
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     const double x = lo + (hi - lo) * ((z >> 11) * 0x1p-53);
-    const double d = ((z & 0x7ff) ? 0.25 : 0.01) * (((z >> 11) & 0xfffff) * 0x1p-20 - 0.5);
+    // shifts up to the bound of the unchecked form, 1/64 (a few much smaller)
+    const double d = ((z & 0x7ff) ? 0x1p-5 : 0x1p-10) * (((z >> 11) & 0xfffff) * 0x1p-20 - 0.5);
     double s, c, s2, c2;
     soax::trig::sincos_fast(x, &s, &c);
     soax::trig::sincos_shift(x, s, c, d, &s2, &c2);
