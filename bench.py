@@ -10,9 +10,12 @@ reported under "rows": the same RK2 workload in the LDS-staged and naive AoS
 layouts, the Euler step at 1e8 particles in all layouts (the HBM headline),
 the wide-record transposes and Euler-with-acceleration steps (3e7),
 checkpointed RK2 forward and forward + adjoint (1e7, 200 steps, k = 20),
-and 256 uneven sets stepped 100 times by one graph of persistent launches
-versus one launch per set (tuned shape).  "copy" is the 16-byte copy
-kernel's bandwidth on 4 GiB, the achievable HBM ceiling.
+256 uneven sets stepped 100 times by one graph of persistent launches
+versus one launch per set (tuned shape), removal of a seeded 1% of the
+headline set by overwriting with the last particle, and fused array
+expressions on the headline set (fused versus one launch per operation).
+"copy" is the 16-byte copy kernel's bandwidth on 4 GiB, the achievable HBM
+ceiling.
 
 Prints ONE JSON line on stdout (progress goes to stderr).
 """
@@ -89,6 +92,23 @@ def bench_rk2(torch, soax, ps, n, nsteps, layout, reps):
             "steps": nsteps * reps}
 
 
+def bench_integrators(torch, soax, ps, n, nsteps=10):
+    """Heun and classical RK4 in the same field and symplectic Euler are not
+    on the headline path; timed on the headline set in the SoA and LDS-staged
+    AoS layouts (60 B per particle-step algorithmic for the field integrators,
+    as for RK2)."""
+    out = {}
+    for integ in ("heun_abc", "rk4_abc"):
+        for lay in ("soa", "aos"):
+            ps.step(lay, integ, 1e-3, 1, abc=[1, 1, 1], wrap=True)
+            with Timer(torch) as t:
+                ps.step(lay, integ, 1e-3, nsteps, abc=[1, 1, 1], wrap=True)
+            per = t.ms / nsteps
+            out[f"{integ}_{lay}"] = {"updates_per_s": rate(n * nsteps, t.ms), "ms_per_launch": per,
+                                     "alg_GBps": gbs(60 * n, per)}
+    return out
+
+
 def bench_euler(torch, soax, ps, n, nsteps, layout):
     ps.step(layout, "euler", 1e-3, 2, wrap=True)
     with Timer(torch) as t:
@@ -111,7 +131,18 @@ def bench_small_euler(torch, soax, si, n=100_000, nsteps=100):
         ps.step(lay, "euler", 1e-3, 10, wrap=True)
         with Timer(torch) as t:
             ps.step(lay, "euler", 1e-3, nsteps, wrap=True)
-        out[lay] = {"updates_per_s": rate(n * nsteps, t.ms), "us_per_step": t.ms * 1e3 / nsteps}
+        # wall time around single-step C-ABI calls: host cost per call, and
+        # call + completion
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            ps.step(lay, "euler", 1e-3, 1, wrap=True)
+        t1 = time.perf_counter()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out[lay] = {"updates_per_s": rate(n * nsteps, t.ms), "us_per_step": t.ms * 1e3 / nsteps,
+                    "call_us": (t1 - t0) * 1e6 / nsteps,
+                    "wall_us_per_step": (t2 - t0) * 1e6 / nsteps}
     ps.close()
     return out
 
@@ -183,6 +214,69 @@ def bench_remove(torch, soax, si, n, frac=0.01, reps=3):
            "particles_per_s": rate(n, ms)}
     ps.close()
     del flags
+    return out
+
+
+def _unfused(torch, soax, E, dst, expr):
+    """Evaluate a program one operation per launch, temporaries in HBM (the
+    separate loops the fused kernel replaces)."""
+    stack = []
+    steps = expr.steps
+    for pos, (op, key, value) in enumerate(steps):
+        if op in (E.ARRAY, E.CONST):
+            stack.append(E.Expr([(op, key, value)]))
+            continue
+        last = pos == len(steps) - 1
+        if op in (E.NEG, E.ABS, E.SQRT):
+            x = stack.pop()
+            node = E.Expr(x.steps + [(op, None, 0.0)])
+        else:
+            b = stack.pop()
+            a = stack.pop()
+            node = E.Expr(a.steps + b.steps + [(op, None, 0.0)])
+        out = dst if last else torch.empty(dst.numel(), dtype=torch.float64, device="cuda")
+        soax.evaluate(out, node)
+        stack.append(E.array(out))
+
+
+def bench_expr(torch, soax, si, n, reps=5):
+    """Fused array expressions on the headline set: the paper's example
+    pos_0 = vel_1 - vel_2 (16 B per particle), and
+    pos_0 = pos_0 + dt * sqrt(vel_0^2 + vel_1^2 + vel_2^2) fused (28 B) versus
+    one launch per operation with double temporaries."""
+    from paper_1710_03462_amd import expr as E
+    ps = soax.ParticleSet(si.BASE_FIELDS, n, aos=False)
+    ps.fill(seed=0)
+    x = ps.array("pos", 0)
+    vx, vy, vz = (ps.array("vel", d) for d in range(3))
+    diff = ps.arr("vel", 1) - ps.arr("vel", 2)
+    ps.assign(("pos", 0), diff)  # compiles
+    with Timer(torch) as t1:
+        for _ in range(reps):
+            ps.assign(("pos", 0), diff)
+    ms_diff = t1.ms / reps
+    speed = E.sqrt(E.array(vx) * E.array(vx) + E.array(vy) * E.array(vy) +
+                   E.array(vz) * E.array(vz))
+    prog = E.array(x) + 1e-3 * speed
+    soax.evaluate(x, prog)
+    _unfused(torch, soax, E, x, prog)
+    with Timer(torch) as t2:
+        for _ in range(reps):
+            soax.evaluate(x, prog)
+    with Timer(torch) as t3:
+        for _ in range(reps):
+            _unfused(torch, soax, E, x, prog)
+    fused, unfused = t2.ms / reps, t3.ms / reps
+    ops = sum(1 for op, _, _ in prog.steps if op not in (E.ARRAY, E.CONST))
+    out = {"n": n,
+           "paper_example": {"expr": "pos0 = vel1 - vel2", "ms": ms_diff,
+                             "alg_GBps": gbs(16 * n, ms_diff)},
+           "fused": {"expr": "pos0 = pos0 + dt*sqrt(vx^2+vy^2+vz^2)", "ms": fused,
+                     "alg_GBps": gbs(28 * n, fused)},
+           "unfused": {"launches": ops, "ms": unfused},
+           "fusion_speedup": unfused / fused}
+    ps.close()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -323,7 +417,7 @@ def main():
     ap.add_argument("--n", type=float, default=1e8, help="particles of the headline workload")
     ap.add_argument("--rows", default="all",
                     help="comma list of extra rows: aos,euler,small,copy,wide,adjoint,batch,"
-                         "remove | all | none")
+                         "remove,expr,integrators | all | none")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--sweep", action="store_true",
                     help="run only the N x SIZE sweep of the paper's GPU experiment and print "
@@ -350,7 +444,8 @@ def main():
         print(json.dumps({"sweep": bench_sweep(torch, soax, si, sizes, ns),
                           "device": torch.cuda.get_device_name(0)}), flush=True)
         return 0
-    rows = {"aos", "euler", "small", "copy", "wide", "adjoint", "batch", "remove"} \
+    rows = {"aos", "euler", "small", "copy", "wide", "adjoint", "batch", "remove", "expr",
+            "integrators"} \
         if args.rows == "all" else \
         set() if args.rows == "none" else set(args.rows.split(","))
     n = int(args.n)
@@ -392,6 +487,9 @@ def main():
             out_rows[f"euler_{lay}"] = bench_euler(torch, soax, ps, n, 20, lay)
         out_rows["euler_soa_over_aos"] = (out_rows["euler_soa"]["updates_per_s"] /
                                           out_rows["euler_aos"]["updates_per_s"])
+    if "integrators" in rows:
+        log("[bench] Heun and RK4 steps at the headline size")
+        out_rows["integrators"] = bench_integrators(torch, soax, ps, n)
     ps.close()
     del ps
     torch.cuda.empty_cache()
@@ -413,6 +511,9 @@ def main():
     if "remove" in rows:
         log("[bench] removal by overwriting with the last particle")
         out_rows["remove"] = bench_remove(torch, soax, si, n)
+    if "expr" in rows:
+        log("[bench] fused array expressions")
+        out_rows["expr"] = bench_expr(torch, soax, si, n)
     torch.cuda.empty_cache()
 
     cpu = None

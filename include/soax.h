@@ -72,11 +72,26 @@ typedef enum { SOAX_SOA = 0, SOAX_AOS = 1, SOAX_AOS_NAIVE = 2 } soax_layout;
  *   SOAX_RK2_ABC    explicit midpoint in the ABC field
  *                   u = (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x):
  *                   xm = x + (dt/2) u(x); x = x + dt u(xm); vel = u(x)   (pos must be f64)
+ *   SOAX_HEUN_ABC   Heun's rule (explicit trapezoid) in the same field:
+ *                   k1 = u(x), k2 = u(x + dt k1); x += (dt/2)(k1 + k2); vel = u(x)
+ *   SOAX_RK4_ABC    classical fourth-order Runge-Kutta in the same field;
+ *                   vel = u(x) at the new position
+ *   SOAX_SYMPLECTIC_EULER  vel += dt * acc first (rounded to vel's type),
+ *                   then pos += dt * vel with the new vel
  * Each step is one full pass over the particles.  A double dt applied to a
  * float property is evaluated in double and rounded on store (C's usual
- * arithmetic conversions); no operation is fused into an FMA.
+ * arithmetic conversions); no operation is fused into an FMA except in the
+ * field integrators' evaluation of the field (the sines and cosines and the
+ * sums of amplitude products), so Euler steps are exact to the last bit.
  */
-typedef enum { SOAX_EULER = 0, SOAX_EULER_ACC = 1, SOAX_RK2_ABC = 2 } soax_integrator;
+typedef enum {
+  SOAX_EULER = 0,
+  SOAX_EULER_ACC = 1,
+  SOAX_RK2_ABC = 2,
+  SOAX_HEUN_ABC = 3,
+  SOAX_RK4_ABC = 4,
+  SOAX_SYMPLECTIC_EULER = 5
+} soax_integrator;
 
 /* Field amplitudes and the periodic wrap of positions into [0, 2*pi)^3
  * (wrap = 1 requires f64 positions: x >= L -> x - L, x < 0 -> x + L, and a

@@ -21,7 +21,7 @@ from . import build as _build
 
 DTYPES = {"i8": (1, np.int8), "u8": (2, np.uint8), "i32": (3, np.int32),
           "i64": (4, np.int64), "f32": (5, np.float32), "f64": (6, np.float64)}
-EULER, EULER_ACC, RK2_ABC = 0, 1, 2
+EULER, EULER_ACC, RK2_ABC, HEUN_ABC, RK4_ABC, SYMPLECTIC_EULER = 0, 1, 2, 3, 4, 5
 
 _lib = None
 

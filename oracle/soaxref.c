@@ -187,6 +187,35 @@ static void rk2_midpoint(const double* abc, double dt, const double* x, double* 
   for (int d = 0; d < 3; ++d) xn[d] = x[d] + dt * k2[d];
 }
 
+/* One Heun (explicit trapezoidal) step: k1 = u(x), k2 = u(x + dt k1),
+ * x+ = x + (dt/2)(k1 + k2). */
+static void heun(const double* abc, double dt, const double* x, double* xn) {
+  double k1[3], xp[3], k2[3];
+  soaxref_field(abc, x, k1);
+  for (int d = 0; d < 3; ++d) xp[d] = x[d] + dt * k1[d];
+  soaxref_field(abc, xp, k2);
+  for (int d = 0; d < 3; ++d) xn[d] = x[d] + (0.5 * dt) * (k1[d] + k2[d]);
+}
+
+/* One classical fourth-order Runge-Kutta step: k1 = u(x), k2 = u(x + dt/2 k1),
+ * k3 = u(x + dt/2 k2), k4 = u(x + dt k3), x+ = x + dt/6 (k1 + 2 k2 + 2 k3 + k4). */
+static void rk4(const double* abc, double dt, const double* x, double* xn) {
+  double k1[3], k2[3], k3[3], k4[3], y[3];
+  soaxref_field(abc, x, k1);
+  for (int d = 0; d < 3; ++d) y[d] = x[d] + (0.5 * dt) * k1[d];
+  soaxref_field(abc, y, k2);
+  for (int d = 0; d < 3; ++d) y[d] = x[d] + (0.5 * dt) * k2[d];
+  soaxref_field(abc, y, k3);
+  for (int d = 0; d < 3; ++d) y[d] = x[d] + dt * k3[d];
+  soaxref_field(abc, y, k4);
+  for (int d = 0; d < 3; ++d)
+    xn[d] = x[d] + (dt / 6.0) * (k1[d] + 2.0 * k2[d] + 2.0 * k3[d] + k4[d]);
+}
+
+static int field_integrator(int integ) {
+  return integ == REF_RK2_ABC || integ == REF_HEUN_ABC || integ == REF_RK4_ABC;
+}
+
 /* Advance particle i by one step of the chosen integrator. */
 static void particle_step(int integ, const vec_view* P, const vec_view* V, const vec_view* Acc,
                           int64_t i, double dt, const double* abc, int wrap) {
@@ -204,9 +233,23 @@ static void particle_step(int integ, const vec_view* P, const vec_view* V, const
         vstore(V, i, d, v + dt * a);
       }
     }
+  } else if (integ == REF_SYMPLECTIC_EULER) {
+    /* the velocity first (stored in its own type), then the position with
+     * the new velocity */
+    for (int d = 0; d < 3; ++d) {
+      vstore(V, i, d, vload(V, i, d) + dt * vload(Acc, i, d));
+      double xn = x[d] + dt * vload(V, i, d);
+      if (wrap) xn = wrap_box(xn);
+      vstore(P, i, d, xn);
+    }
   } else {
     double xn[3], un[3];
-    rk2_midpoint(abc, dt, x, xn);
+    if (integ == REF_RK2_ABC)
+      rk2_midpoint(abc, dt, x, xn);
+    else if (integ == REF_HEUN_ABC)
+      heun(abc, dt, x, xn);
+    else
+      rk4(abc, dt, x, xn);
     if (wrap)
       for (int d = 0; d < 3; ++d) xn[d] = wrap_box(xn[d]);
     for (int d = 0; d < 3; ++d) vstore(P, i, d, xn[d]);
@@ -218,8 +261,8 @@ static void particle_step(int integ, const vec_view* P, const vec_view* V, const
 static int check_step_args(const ref_schema* s, int64_t n, int integ, double dt, int64_t nsteps,
                            const double* abc, int wrap) {
   if (n < 0 || nsteps < 0 || !isfinite(dt)) return -1;
-  if (integ < REF_EULER || integ > REF_RK2_ABC) return -1;
-  if (integ == REF_RK2_ABC) {
+  if (integ < REF_EULER || integ > REF_SYMPLECTIC_EULER) return -1;
+  if (field_integrator(integ)) {
     if (!abc || !isfinite(abc[0]) || !isfinite(abc[1]) || !isfinite(abc[2])) return -1;
     int f = find_field(s, "pos");
     if (f < 0 || s->dtypes[f] != REF_F64) return -2;
@@ -252,7 +295,9 @@ int soaxref_step_soa(const ref_schema* s, int64_t n, void* const* soa, int integ
   vec_view P, V, Acc;
   if ((rc = soa_view(s, soa, "pos", &P))) return rc;
   if ((rc = soa_view(s, soa, "vel", &V))) return rc;
-  if (integ == REF_EULER_ACC && (rc = soa_view(s, soa, "acc", &Acc))) return rc;
+  if ((integ == REF_EULER_ACC || integ == REF_SYMPLECTIC_EULER) &&
+      (rc = soa_view(s, soa, "acc", &Acc)))
+    return rc;
   return run_steps(s, n, &P, &V, &Acc, integ, dt, nsteps, abc, wrap);
 }
 
@@ -265,7 +310,9 @@ int soaxref_step_aos(const ref_schema* s, int64_t n, void* aos, int integ, doubl
   vec_view P, V, Acc;
   if ((rc = aos_view(s, aos, "pos", &P))) return rc;
   if ((rc = aos_view(s, aos, "vel", &V))) return rc;
-  if (integ == REF_EULER_ACC && (rc = aos_view(s, aos, "acc", &Acc))) return rc;
+  if ((integ == REF_EULER_ACC || integ == REF_SYMPLECTIC_EULER) &&
+      (rc = aos_view(s, aos, "acc", &Acc)))
+    return rc;
   return run_steps(s, n, &P, &V, &Acc, integ, dt, nsteps, abc, wrap);
 }
 

@@ -28,7 +28,14 @@ extern "C" {
 enum { REF_I8 = 1, REF_U8 = 2, REF_I32 = 3, REF_I64 = 4, REF_F32 = 5, REF_F64 = 6 };
 
 /* Integrators. */
-enum { REF_EULER = 0, REF_EULER_ACC = 1, REF_RK2_ABC = 2 };
+enum {
+  REF_EULER = 0,
+  REF_EULER_ACC = 1,
+  REF_RK2_ABC = 2,
+  REF_HEUN_ABC = 3,
+  REF_RK4_ABC = 4,
+  REF_SYMPLECTIC_EULER = 5
+};
 
 /*
  * A particle schema: an ordered list of named properties, each an element

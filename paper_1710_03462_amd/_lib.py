@@ -17,8 +17,9 @@ STATUS = {-1: "SOAX_E_ARG", -2: "SOAX_E_SCHEMA", -3: "SOAX_E_RANGE", -4: "SOAX_E
 DTYPE = {"i8": 1, "u8": 2, "i32": 3, "i64": 4, "f32": 5, "f64": 6}
 SOA, AOS, AOS_NAIVE = 0, 1, 2
 LAYOUTS = {"soa": SOA, "aos": AOS, "aos_naive": AOS_NAIVE}
-EULER, EULER_ACC, RK2_ABC = 0, 1, 2
-INTEGRATORS = {"euler": EULER, "euler_acc": EULER_ACC, "rk2_abc": RK2_ABC}
+EULER, EULER_ACC, RK2_ABC, HEUN_ABC, RK4_ABC, SYMPLECTIC_EULER = 0, 1, 2, 3, 4, 5
+INTEGRATORS = {"euler": EULER, "euler_acc": EULER_ACC, "rk2_abc": RK2_ABC, "heun_abc": HEUN_ABC,
+               "rk4_abc": RK4_ABC, "symplectic_euler": SYMPLECTIC_EULER}
 
 
 class SoaxError(RuntimeError):

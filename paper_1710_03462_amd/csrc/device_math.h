@@ -187,6 +187,9 @@ __device__ __forceinline__ double widen(T v) {
 // update_particle, one coordinate at a time.
 template <int INTEG, typename PT, typename VT>
 __device__ __forceinline__ void euler_component(PT& x, VT& v, VT a, double dt, int wrap) {
+  // symplectic Euler: the velocity first, rounded to its type, then the
+  // position with the new velocity
+  if constexpr (INTEG == kSymEuler) v = static_cast<VT>(widen(v) + dt * widen(a));
   double y = widen(x) + dt * widen(v);
   if constexpr (std::is_same<PT, double>::value) {
     if (wrap) y = wrap_box(y);
@@ -195,13 +198,51 @@ __device__ __forceinline__ void euler_component(PT& x, VT& v, VT a, double dt, i
   if constexpr (INTEG == kEulerAcc) v = static_cast<VT>(widen(v) + dt * widen(a));
 }
 
+// One Heun step (explicit trapezoid): k1 = u(x), k2 = u(x + dt k1),
+// d = (dt/2)(k1 + k2); t holds the start point's sines and cosines.
+template <bool SMALL>
+__device__ __forceinline__ void heun_parts(const Abc& p, double dt, double x, double y, double z,
+                                           Trig3& t, double& d0, double& d1, double& d2) {
+  t = trig3(x, y, z);
+  double a0, a1, a2, b0, b1, b2;
+  field_of(p, t, a0, a1, a2);
+  field_of(p, trig3_shift<SMALL>(t, x, y, z, dt * a0, dt * a1, dt * a2), b0, b1, b2);
+  const double h = 0.5 * dt;
+  d0 = h * (a0 + b0);
+  d1 = h * (a1 + b1);
+  d2 = h * (a2 + b2);
+}
+
+// One classical RK4 step: k1 = u(x), k2 = u(x + dt/2 k1), k3 = u(x + dt/2 k2),
+// k4 = u(x + dt k3), d = dt/6 (k1 + 2 k2 + 2 k3 + k4); every stage's sines come
+// from the start point's by angle addition.
+template <bool SMALL>
+__device__ __forceinline__ void rk4_parts(const Abc& p, double dt, double x, double y, double z,
+                                          Trig3& t, double& d0, double& d1, double& d2) {
+  t = trig3(x, y, z);
+  const double h = 0.5 * dt;
+  double k10, k11, k12, k20, k21, k22, k30, k31, k32, k40, k41, k42;
+  field_of(p, t, k10, k11, k12);
+  field_of(p, trig3_shift<SMALL>(t, x, y, z, h * k10, h * k11, h * k12), k20, k21, k22);
+  field_of(p, trig3_shift<SMALL>(t, x, y, z, h * k20, h * k21, h * k22), k30, k31, k32);
+  field_of(p, trig3_shift<SMALL>(t, x, y, z, dt * k30, dt * k31, dt * k32), k40, k41, k42);
+  const double s = dt / 6.0;
+  d0 = s * (k10 + 2.0 * k20 + 2.0 * k30 + k40);
+  d1 = s * (k11 + 2.0 * k21 + 2.0 * k31 + k41);
+  d2 = s * (k12 + 2.0 * k22 + 2.0 * k32 + k42);
+}
+
 // Advance one particle.  Positions and velocities are widened to double,
 // combined in double and rounded back on store.  SMALL: small_steps holds.
 template <int INTEG, typename PT, typename VT, bool SMALL>
 __device__ __forceinline__ void update_particle(PT& x0, PT& x1, PT& x2, VT& v0, VT& v1, VT& v2,
                                                 VT a0, VT a1, VT a2, double dt, const Abc& p,
                                                 int wrap) {
-  if constexpr (INTEG == kEuler || INTEG == kEulerAcc) {
+  if constexpr (INTEG == kSymEuler) {
+    euler_component<INTEG, PT, VT>(x0, v0, a0, dt, wrap);
+    euler_component<INTEG, PT, VT>(x1, v1, a1, dt, wrap);
+    euler_component<INTEG, PT, VT>(x2, v2, a2, dt, wrap);
+  } else if constexpr (INTEG == kEuler || INTEG == kEulerAcc) {
     double y0 = widen(x0) + dt * widen(v0);
     double y1 = widen(x1) + dt * widen(v1);
     double y2 = widen(x2) + dt * widen(v2);
@@ -225,7 +266,15 @@ __device__ __forceinline__ void update_particle(PT& x0, PT& x1, PT& x2, VT& v0, 
     double y0 = s0, y1 = s1, y2 = s2;
     Trig3 t;
     double d0, d1, d2;
-    rk2_midpoint_parts<SMALL>(p, dt, y0, y1, y2, t, d0, d1, d2);
+    if constexpr (INTEG == kRk2Abc) {
+      rk2_midpoint_parts<SMALL>(p, dt, y0, y1, y2, t, d0, d1, d2);
+    } else {
+      if constexpr (INTEG == kHeunAbc) heun_parts<SMALL>(p, dt, s0, s1, s2, t, d0, d1, d2);
+      else rk4_parts<SMALL>(p, dt, s0, s1, s2, t, d0, d1, d2);
+      y0 = s0 + d0;
+      y1 = s1 + d1;
+      y2 = s2 + d2;
+    }
     if (wrap) {
       y0 = wrap_box(y0);
       y1 = wrap_box(y1);

@@ -48,10 +48,10 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
   const VT* ax = static_cast<const VT*>(a.acc[0]);
   const VT* ay = static_cast<const VT*>(a.acc[1]);
   const VT* az = static_cast<const VT*>(a.acc[2]);
-  constexpr bool kReadsVel = INTEG != kRk2Abc;  // RK2 overwrites vel without reading it
+  constexpr bool kReadsVel = !field_integrator(INTEG);  // field steps overwrite vel unread
   constexpr bool kNtVelLoad = STREAM && INTEG == kEuler;  // read-only in Euler steps
 
-  if constexpr (INTEG != kRk2Abc) {
+  if constexpr (!field_integrator(INTEG)) {
     if (i0 + VEC <= a.n) {
       // Euler steps are independent per coordinate: one component at a time
       // (its loads, update and stores) keeps two or three streams per wave
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
         PT x[VEC];
         VT v[VEC], g[VEC];
         ld_run<false, PT, VEC>(P[d] + i0, x);
-        if constexpr (INTEG == kEulerAcc) {
+        if constexpr (uses_acc(INTEG)) {
           ld_run<false, VT, VEC>(Vv[d] + i0, v);
           ld_run<STREAM, VT, VEC>(G[d] + i0, g);
         } else {
@@ -72,10 +72,10 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
         }
 #pragma unroll
         for (int j = 0; j < VEC; ++j)
-          euler_component<INTEG, PT, VT>(x[j], v[j], INTEG == kEulerAcc ? g[j] : VT(0), a.dt,
+          euler_component<INTEG, PT, VT>(x[j], v[j], uses_acc(INTEG) ? g[j] : VT(0), a.dt,
                                          a.wrap);
         st_run<STREAM, PT, VEC>(P[d] + i0, x);
-        if constexpr (INTEG == kEulerAcc) st_run<STREAM, VT, VEC>(Vv[d] + i0, v);
+        if constexpr (uses_acc(INTEG)) st_run<STREAM, VT, VEC>(Vv[d] + i0, v);
       }
       return;
     }
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
       ld_run<kNtVelLoad, VT, VEC>(vy + i0, v);
       ld_run<kNtVelLoad, VT, VEC>(vz + i0, w);
     }
-    if constexpr (INTEG == kEulerAcc) {
+    if constexpr (uses_acc(INTEG)) {
       ld_run<STREAM, VT, VEC>(ax + i0, ga);
       ld_run<STREAM, VT, VEC>(ay + i0, gb);
       ld_run<STREAM, VT, VEC>(az + i0, gc);
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
       VT u = kReadsVel ? vx[i] : VT(0), v = kReadsVel ? vy[i] : VT(0),
          w = kReadsVel ? vz[i] : VT(0);
       VT g0 = VT(0), g1 = VT(0), g2 = VT(0);
-      if constexpr (INTEG == kEulerAcc) {
+      if constexpr (uses_acc(INTEG)) {
         g0 = ax[i];
         g1 = ay[i];
         g2 = az[i];
@@ -140,6 +140,12 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
 
 template <int INTEG, typename PT, typename VT, bool SMALL, bool STREAM>
 hipError_t soa_step_launch(int vec, int64_t grid, int block, const SoaStepArgs& a, hipStream_t s) {
+  if constexpr (INTEG == kHeunAbc || INTEG == kRk4Abc) {
+    // one particle per thread only (the host forces vec = 1 for these)
+    hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 1, SMALL, STREAM>), dim3(grid), dim3(block),
+                       0, s, a);
+    return hipGetLastError();
+  }
   switch (vec) {
     case 1:
       hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 1, SMALL, STREAM>), dim3(grid),
@@ -166,13 +172,14 @@ hipError_t soa_step_stream(bool stream, int vec, int64_t grid, int block, const 
 
 template <int INTEG, typename PT, typename VT>
 hipError_t soa_step_vec(int vec, int block, const SoaStepArgs& a, hipStream_t s) {
+  if constexpr (INTEG == kHeunAbc || INTEG == kRk4Abc) vec = 1;
   const int64_t threads = (a.n + vec - 1) / vec;
   const int64_t grid = (threads + block - 1) / block;
   if (grid == 0) return hipSuccess;
   int64_t bytes = 3 * (sizeof(PT) + sizeof(VT));
-  if (INTEG == kEulerAcc) bytes += 3 * sizeof(VT);
+  if (uses_acc(INTEG)) bytes += 3 * sizeof(VT);
   const bool stream = a.n * bytes >= kStreamBytes;
-  if constexpr (INTEG == kRk2Abc) {
+  if constexpr (field_integrator(INTEG)) {
     if (small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C))
       return soa_step_stream<INTEG, PT, VT, true>(stream, vec, grid, block, a, s);
   }
@@ -209,12 +216,12 @@ __device__ __forceinline__ void update_record(char* rec, const AosStepArgs& a, c
   PT x = rec_load<PT, ALIGNED>(P), y = rec_load<PT, ALIGNED>(P + sizeof(PT)),
      z = rec_load<PT, ALIGNED>(P + 2 * sizeof(PT));
   VT u = VT(0), v = VT(0), w = VT(0), g0 = VT(0), g1 = VT(0), g2 = VT(0);
-  if constexpr (INTEG != kRk2Abc) {
+  if constexpr (!field_integrator(INTEG)) {
     u = rec_load<VT, ALIGNED>(V);
     v = rec_load<VT, ALIGNED>(V + sizeof(VT));
     w = rec_load<VT, ALIGNED>(V + 2 * sizeof(VT));
   }
-  if constexpr (INTEG == kEulerAcc) {
+  if constexpr (uses_acc(INTEG)) {
     const char* G = rec + a.off_acc;
     g0 = rec_load<VT, ALIGNED>(G);
     g1 = rec_load<VT, ALIGNED>(G + sizeof(VT));
@@ -315,7 +322,7 @@ hipError_t aos_step_launch(bool aligned, bool naive, int block, const AosStepArg
 template <int INTEG, typename PT, typename VT>
 hipError_t aos_step_t(bool aligned, bool naive, int block, const AosStepArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  if constexpr (INTEG == kRk2Abc) {
+  if constexpr (field_integrator(INTEG)) {
     if (small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C))
       return aos_step_launch<INTEG, PT, VT, true>(aligned, naive, block, a, s);
   }
@@ -327,7 +334,7 @@ hipError_t aos_dispatch(int pos_t, int vel_t, bool aligned, bool naive, int bloc
                         const AosStepArgs& a, hipStream_t s) {
   if (pos_t == kF64 && vel_t == kF32) return aos_step_t<INTEG, double, float>(aligned, naive, block, a, s);
   if (pos_t == kF64 && vel_t == kF64) return aos_step_t<INTEG, double, double>(aligned, naive, block, a, s);
-  if constexpr (INTEG != kRk2Abc) {
+  if constexpr (!field_integrator(INTEG)) {
     if (pos_t == kF32 && vel_t == kF32) return aos_step_t<INTEG, float, float>(aligned, naive, block, a, s);
     if (pos_t == kF32 && vel_t == kF64) return aos_step_t<INTEG, float, double>(aligned, naive, block, a, s);
   }
@@ -540,6 +547,19 @@ hipError_t launch_soa_step(int integ, int pos_t, int vel_t, int vec, int block,
       if (!pd) return hipErrorInvalidValue;
       if (vd) return soa_step_vec<kRk2Abc, double, double>(vec, block, a, s);
       return soa_step_vec<kRk2Abc, double, float>(vec, block, a, s);
+    case kHeunAbc:
+      if (!pd) return hipErrorInvalidValue;
+      if (vd) return soa_step_vec<kHeunAbc, double, double>(vec, block, a, s);
+      return soa_step_vec<kHeunAbc, double, float>(vec, block, a, s);
+    case kRk4Abc:
+      if (!pd) return hipErrorInvalidValue;
+      if (vd) return soa_step_vec<kRk4Abc, double, double>(vec, block, a, s);
+      return soa_step_vec<kRk4Abc, double, float>(vec, block, a, s);
+    case kSymEuler:
+      if (pd && !vd) return soa_step_vec<kSymEuler, double, float>(vec, block, a, s);
+      if (pd && vd) return soa_step_vec<kSymEuler, double, double>(vec, block, a, s);
+      if (!pd && !vd) return soa_step_vec<kSymEuler, float, float>(vec, block, a, s);
+      return soa_step_vec<kSymEuler, float, double>(vec, block, a, s);
     default:
       return hipErrorInvalidValue;
   }
@@ -559,6 +579,9 @@ static hipError_t aos_any(int integ, int pos_t, int vel_t, bool aligned, bool na
     case kEuler: return aos_dispatch<kEuler>(pos_t, vel_t, aligned, naive, block, a, s);
     case kEulerAcc: return aos_dispatch<kEulerAcc>(pos_t, vel_t, aligned, naive, block, a, s);
     case kRk2Abc: return aos_dispatch<kRk2Abc>(pos_t, vel_t, aligned, naive, block, a, s);
+    case kHeunAbc: return aos_dispatch<kHeunAbc>(pos_t, vel_t, aligned, naive, block, a, s);
+    case kRk4Abc: return aos_dispatch<kRk4Abc>(pos_t, vel_t, aligned, naive, block, a, s);
+    case kSymEuler: return aos_dispatch<kSymEuler>(pos_t, vel_t, aligned, naive, block, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -17,7 +17,13 @@ constexpr int kMaxArrays = 3 * kMaxFields;
 
 // Element type codes (same values as soax_dtype).
 enum Dtype : int32_t { kI8 = 1, kU8 = 2, kI32 = 3, kI64 = 4, kF32 = 5, kF64 = 6 };
-enum Integrator : int32_t { kEuler = 0, kEulerAcc = 1, kRk2Abc = 2 };
+enum Integrator : int32_t {
+  kEuler = 0, kEulerAcc = 1, kRk2Abc = 2, kHeunAbc = 3, kRk4Abc = 4, kSymEuler = 5
+};
+// Integrators that evaluate the ABC field (need f64 positions and amplitudes).
+constexpr bool field_integrator(int i) { return i == kRk2Abc || i == kHeunAbc || i == kRk4Abc; }
+// Integrators that read an acceleration property.
+constexpr bool uses_acc(int i) { return i == kEulerAcc || i == kSymEuler; }
 
 inline int dtype_size(int32_t t) {
   switch (t) {

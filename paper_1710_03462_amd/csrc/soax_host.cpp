@@ -424,7 +424,7 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
                       const soax_params* params, void* stream) {
   if (!set) return fail(SOAX_E_ARG, "set is NULL");
   if (layout < SOAX_SOA || layout > SOAX_AOS_NAIVE) return fail(SOAX_E_ARG, "unknown layout %d", layout);
-  if (integrator < SOAX_EULER || integrator > SOAX_RK2_ABC)
+  if (integrator < SOAX_EULER || integrator > SOAX_SYMPLECTIC_EULER)
     return fail(SOAX_E_ARG, "unknown integrator %d", integrator);
   if (!is_finite(dt)) return fail(SOAX_E_ARG, "dt is not finite");
   if (nsteps < 0) return fail(SOAX_E_ARG, "nsteps is negative");
@@ -432,7 +432,7 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
   int fp, fv, fa = -1;
   soax_status st;
   if ((st = vec_field(L, "pos", &fp)) || (st = vec_field(L, "vel", &fv))) return st;
-  if (integrator == SOAX_EULER_ACC) {
+  if (uses_acc(integrator)) {
     if ((st = vec_field(L, "acc", &fa))) return st;
     if (L.f[fa].dtype != L.f[fv].dtype)
       return fail(SOAX_E_SCHEMA, "'acc' must have the same type as 'vel'");
@@ -440,9 +440,9 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
   const int wrap = params ? params->wrap : 0;
   if (wrap != 0 && wrap != 1) return fail(SOAX_E_ARG, "params.wrap must be 0 or 1");
   AbcParams abc{0.0, 0.0, 0.0};
-  if (integrator == SOAX_RK2_ABC) {
-    if (!params) return fail(SOAX_E_ARG, "RK2 in the ABC field needs params");
-    if (L.f[fp].dtype != kF64) return fail(SOAX_E_SCHEMA, "RK2 in the ABC field needs f64 'pos'");
+  if (field_integrator(integrator)) {
+    if (!params) return fail(SOAX_E_ARG, "integrating in the ABC field needs params");
+    if (L.f[fp].dtype != kF64) return fail(SOAX_E_SCHEMA, "integrating in the ABC field needs f64 'pos'");
   }
   if (params) {
     if (!is_finite(params->A) || !is_finite(params->B) || !is_finite(params->C))

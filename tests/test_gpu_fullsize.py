@@ -73,6 +73,38 @@ def test_config1_rk2_1e8(ref):
     ps.close()
 
 
+def test_config1_integrator_variants_1e8(ref):
+    """Heun and RK4 on the headline set, as the benchmark's integrator row
+    runs them (SoA, then the LDS-staged AoS copy), sampled against the oracle."""
+    n, abc = 100_000_000, [1.0, 1.0, 1.0]
+    fields = si.BASE_FIELDS
+    sch = ref.Schema(fields)
+    ps = soax.ParticleSet(fields, n)
+    ps.fill(seed=0, vel_mode=1, abc=abc)
+    ps.soa_to_aos()
+    ranges = sample_ranges(n, width=64)
+    init = {r0: ref.fill_range(sch, r0, cnt, seed=0, vel_mode=1, abc=abc) for r0, cnt in ranges}
+    ps.step("soa", "heun_abc", 1e-3, 3, abc=abc, wrap=True)
+    ps.step("soa", "rk4_abc", 1e-3, 3, abc=abc, wrap=True)
+    ps.step("aos", "heun_abc", 1e-3, 3, abc=abc, wrap=True)
+    ps.step("aos", "rk4_abc", 1e-3, 3, abc=abc, wrap=True)
+    torch.cuda.synchronize()
+    rec = ps.aos[: n * ps.stride].view(n, ps.stride)
+    for d in range(3):  # the two layouts ran the same arithmetic
+        pos_aos = rec[:, 8 + 8 * d: 16 + 8 * d].contiguous().view(torch.float64).view(-1)
+        assert torch.equal(pos_aos, ps.soa[1 + d])
+    del rec, pos_aos
+    for r0, cnt in ranges:
+        want = [a.copy() for a in init[r0]]
+        ref.step_soa(sch, want, ref.HEUN_ABC, 1e-3, 3, abc=abc, wrap=True)
+        ref.step_soa(sch, want, ref.RK4_ABC, 1e-3, 3, abc=abc, wrap=True)
+        got = gpu_slice(ps, r0, cnt)
+        for d in range(3):
+            assert_positions_close(got[1 + d], want[1 + d])
+            assert_fields_close(got[4 + d], want[4 + d])
+    ps.close()
+
+
 def test_config2_wide_transpose_and_steps_3e7(ref):
     n = 30_000_000
     fields = si.WIDE_FIELDS

@@ -318,3 +318,54 @@ def test_rk2_large_steps_use_checked_shifts(ref, layout, dt):
     for d in range(3):
         assert_positions_close(got[1 + d], want[1 + d])
         assert_fields_close(got[4 + d], want[4 + d])
+
+
+# ------------------------------------------------------ integrator variants
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("integ", ["heun_abc", "rk4_abc"])
+@pytest.mark.parametrize("n", [5, 4099])
+def test_field_integrators_match_oracle(ref, layout, integ, n):
+    fields = si.BASE_FIELDS
+    arrays = si.random_state(fields, n, 40 + n)
+    abc = [1.0, 0.8, 0.6]
+    got = run_gpu(fields, arrays, layout, integ, 2e-3, 7, abc=abc)
+    want = run_ref(ref, fields, arrays, getattr(ref, integ.upper()), 2e-3, 7, abc=abc)
+    assert np.array_equal(got[0], want[0])
+    for d in range(3):
+        assert_positions_close(got[1 + d], want[1 + d])
+        assert_fields_close(got[4 + d], want[4 + d])
+
+
+@pytest.mark.parametrize("integ", ["heun_abc", "rk4_abc"])
+def test_field_integrators_large_steps_and_f64_velocity(ref, integ):
+    # dt (|A|+|B|+|C|) above the unchecked shift bound: per-lane checked shifts
+    fields = [("id", "i32", 1), ("pos", "f64", 3), ("vel", "f64", 3)]
+    arrays = si.random_state(fields, 1000, 3)
+    abc = [1.0, 1.0, 1.0]
+    for layout in LAYOUTS:
+        got = run_gpu(fields, arrays, layout, integ, 0.05, 3, abc=abc)
+        want = run_ref(ref, fields, arrays, getattr(ref, integ.upper()), 0.05, 3, abc=abc)
+        for d in range(3):
+            assert_positions_close(got[1 + d], want[1 + d])
+            assert np.abs(got[4 + d] - want[4 + d]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("packed", [False, True])
+def test_symplectic_euler_bit_exact(ref, layout, packed):
+    fields = si.WIDE_FIELDS
+    arrays = si.random_state(fields, 4099, 77)
+    got = run_gpu(fields, arrays, layout, "symplectic_euler", 1e-3, 9, packed=packed)
+    want = run_ref(ref, fields, arrays, ref.SYMPLECTIC_EULER, 1e-3, 9)
+    for a, (g, w) in enumerate(zip(got, want)):
+        assert np.array_equal(g, w), a
+
+
+def test_symplectic_euler_float_record(ref):
+    fields = [("pos", "f32", 3), ("vel", "f32", 3), ("acc", "f32", 3)]
+    arrays = si.random_state(fields, 257, 5)
+    for layout in LAYOUTS:
+        got = run_gpu(fields, arrays, layout, "symplectic_euler", 1e-2, 4, wrap=False)
+        want = run_ref(ref, fields, arrays, ref.SYMPLECTIC_EULER, 1e-2, 4, wrap=False)
+        assert all(np.array_equal(g, w) for g, w in zip(got, want))
