@@ -203,7 +203,10 @@ soax_status soax_get_record(const soax_set* set, int32_t layout, int64_t i, void
  * the two copies consistent if they were.  A set that changes its size or
  * buffers (any call below but soax_capacity and soax_set_record) invalidates
  * every batch that holds it: such a batch's calls then fail with STATE.
- * All of them synchronise `stream` before returning.
+ * Growing past the capacity, push_back and rebind synchronise `stream`
+ * before returning; removal waits once for its flag count (the new size is
+ * returned) and leaves the moves enqueued; resize within the capacity only
+ * enqueues its zero fill.
  */
 
 /* Host query of the particle count and the capacity. */
@@ -240,7 +243,8 @@ soax_status soax_set_record(soax_set* set, int64_t i, const void* host_record);
 
 /*
  * Remove every particle i < n with flags[i] != 0 (device, n bytes; not
- * modified) by overwriting it with the last particle, the removal of
+ * modified; it may be reused once the stream has passed this call) by
+ * overwriting it with the last particle, the removal of
  * Section 2 for sets whose order does not matter.  The result equals the
  * sequential rule "while particle i is flagged, copy the last particle over
  * it and drop the last", computed as: the flagged slots below n' = n - m

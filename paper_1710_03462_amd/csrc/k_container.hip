@@ -130,23 +130,32 @@ struct WordOf<16> {
   using T = Word16;
 };
 
-// One thread per (move, word): element hole_at[k] <- element mover_at[k],
-// words_per elements of W bytes each.  Holes lie below the new size and
+// Grid (moves, arrays): thread x of row y moves words of element
+// hole_at[k] <- mover_at[k] of array y.  Holes lie below the new size and
 // movers at or above it, so no thread reads what another writes.
 template <int W>
-__global__ __launch_bounds__(kBlock) void move_kernel(char* __restrict__ arr, int64_t stride,
-                                                      int words_per,
-                                                      const int64_t* __restrict__ hole_at,
-                                                      const int64_t* __restrict__ mover_at,
-                                                      const int64_t* __restrict__ nmoves) {
+__device__ __forceinline__ void move_words(char* base, int64_t stride, int64_t h, int64_t m) {
   using T = typename WordOf<W>::T;
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t k = t / words_per;
-  const int w = static_cast<int>(t - k * words_per);
+  T* dst = reinterpret_cast<T*>(base + h * stride);
+  const T* src = reinterpret_cast<const T*>(base + m * stride);
+  const int words = static_cast<int>(stride / W);
+  for (int w = 0; w < words; ++w) dst[w] = src[w];
+}
+
+__global__ __launch_bounds__(kBlock) void move_all_kernel(MoveArgs a,
+                                                          const int64_t* __restrict__ hole_at,
+                                                          const int64_t* __restrict__ mover_at,
+                                                          const int64_t* __restrict__ nmoves) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= *nmoves) return;
-  T* dst = reinterpret_cast<T*>(arr + hole_at[k] * stride) + w;
-  const T* src = reinterpret_cast<const T*>(arr + mover_at[k] * stride) + w;
-  *dst = *src;
+  const int y = blockIdx.y;
+  const int64_t h = hole_at[k], m = mover_at[k];
+  switch (a.word[y]) {
+    case 16: move_words<16>(a.base[y], a.stride[y], h, m); break;
+    case 8: move_words<8>(a.base[y], a.stride[y], h, m); break;
+    case 4: move_words<4>(a.base[y], a.stride[y], h, m); break;
+    default: move_words<1>(a.base[y], a.stride[y], h, m); break;
+  }
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(char* __restrict__ p, int64_t bytes) {
@@ -176,25 +185,16 @@ hipError_t launch_rank_flags(const uint8_t* flags, int64_t n, int64_t n_new,
   return hipGetLastError();
 }
 
-hipError_t launch_move(void* arr, int64_t stride, int word, const int64_t* hole_at,
-                       const int64_t* mover_at, const int64_t* nmoves, int64_t max_moves,
-                       hipStream_t s) {
-  if (max_moves <= 0) return hipSuccess;
-  if (word != 1 && word != 4 && word != 8 && word != 16) return hipErrorInvalidValue;
-  if (stride % word) return hipErrorInvalidValue;
-  const int words_per = static_cast<int>(stride / word);
-  const int64_t grid = (max_moves * words_per + kBlock - 1) / kBlock;
-  char* a = static_cast<char*>(arr);
-#define SOAX_MOVE(W)                                                                             \
-  hipLaunchKernelGGL(move_kernel<W>, dim3(grid), dim3(kBlock), 0, s, a, stride, words_per, hole_at, \
-                     mover_at, nmoves)
-  switch (word) {
-    case 16: SOAX_MOVE(16); break;
-    case 8: SOAX_MOVE(8); break;
-    case 4: SOAX_MOVE(4); break;
-    default: SOAX_MOVE(1); break;
+hipError_t launch_move_all(const MoveArgs& m, const int64_t* hole_at, const int64_t* mover_at,
+                           const int64_t* nmoves, int64_t max_moves, hipStream_t s) {
+  if (max_moves <= 0 || m.narrays <= 0) return hipSuccess;
+  for (int y = 0; y < m.narrays; ++y) {
+    const int w = m.word[y];
+    if ((w != 1 && w != 4 && w != 8 && w != 16) || m.stride[y] % w) return hipErrorInvalidValue;
   }
-#undef SOAX_MOVE
+  const int64_t grid = (max_moves + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(move_all_kernel, dim3(grid, m.narrays), dim3(kBlock), 0, s, m, hole_at,
+                     mover_at, nmoves);
   return hipGetLastError();
 }
 

@@ -370,12 +370,12 @@ __device__ __forceinline__ void copy_es(char* dst, const char* src, int es) {
 // store consecutive elements.
 template <bool ALIGNED, bool STREAM>
 __global__ __launch_bounds__(256) void aos_to_soa_kernel(const XposeArgs* __restrict__ tp,
-                                                         int tile) {
+                                                         int64_t n, int tile) {
   extern __shared__ uint4 lds_u4[];
   char* lds = reinterpret_cast<char*>(lds_u4);
   const XposeArgs& t = *tp;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * tile;
-  const int nrec = static_cast<int>(min(static_cast<int64_t>(tile), t.n - r0));
+  const int nrec = static_cast<int>(min(static_cast<int64_t>(tile), n - r0));
   const int stride = t.stride;
   stage_in<STREAM>(lds, t.aos + r0 * stride, nrec * stride);
   __syncthreads();
@@ -404,12 +404,12 @@ __global__ __launch_bounds__(256) void aos_to_soa_kernel(const XposeArgs* __rest
 // coalesced 16-byte stores.
 template <bool ALIGNED, bool STREAM>
 __global__ __launch_bounds__(256) void soa_to_aos_kernel(const XposeArgs* __restrict__ tp,
-                                                         int tile) {
+                                                         int64_t n, int tile) {
   extern __shared__ uint4 lds_u4[];
   char* lds = reinterpret_cast<char*>(lds_u4);
   const XposeArgs& t = *tp;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * tile;
-  const int nrec = static_cast<int>(min(static_cast<int64_t>(tile), t.n - r0));
+  const int nrec = static_cast<int>(min(static_cast<int64_t>(tile), n - r0));
   const int stride = t.stride;
   const int nbytes = nrec * stride;
   for (int c = threadIdx.x; c < (nbytes + 15) >> 4; c += blockDim.x)
@@ -611,13 +611,13 @@ hipError_t launch_xpose(bool to_soa, const XposeArgs& host, const XposeArgs* dev
   const bool stream = host.n * host.stride >= kStreamBytes;
 #define SOAX_XPOSE(KER)                                                                       \
   if (host.aligned && stream)                                                                 \
-    hipLaunchKernelGGL((KER<true, true>), dim3(grid), dim3(256), lds, s, dev, tile);          \
+    hipLaunchKernelGGL((KER<true, true>), dim3(grid), dim3(256), lds, s, dev, host.n, tile);  \
   else if (host.aligned)                                                                      \
-    hipLaunchKernelGGL((KER<true, false>), dim3(grid), dim3(256), lds, s, dev, tile);         \
+    hipLaunchKernelGGL((KER<true, false>), dim3(grid), dim3(256), lds, s, dev, host.n, tile); \
   else if (stream)                                                                            \
-    hipLaunchKernelGGL((KER<false, true>), dim3(grid), dim3(256), lds, s, dev, tile);         \
+    hipLaunchKernelGGL((KER<false, true>), dim3(grid), dim3(256), lds, s, dev, host.n, tile); \
   else                                                                                        \
-    hipLaunchKernelGGL((KER<false, false>), dim3(grid), dim3(256), lds, s, dev, tile);
+    hipLaunchKernelGGL((KER<false, false>), dim3(grid), dim3(256), lds, s, dev, host.n, tile);
   if (to_soa) {
     SOAX_XPOSE(aos_to_soa_kernel)
   } else {

@@ -94,7 +94,7 @@ int aos_tile_records(int stride, int block);
 
 struct XposeArgs {
   char* aos;
-  int64_t n;
+  int64_t n;  // particles to move; the kernels take it as an argument, not from the table
   int32_t stride;
   int32_t narrays;
   int32_t aligned;  // every element naturally aligned inside the record
@@ -104,7 +104,7 @@ struct XposeArgs {
 };
 
 // `host` is a host copy of the table the kernels read from `dev` (device
-// memory, uploaded once per set).
+// memory, uploaded when the set's buffers change); host.n is passed by value.
 hipError_t launch_xpose(bool to_soa, const XposeArgs& host, const XposeArgs* dev, hipStream_t s);
 
 // -------------------------------------------------------------------- fill
@@ -194,12 +194,18 @@ hipError_t launch_count_flags(const uint8_t* flags, int64_t n, int32_t* counts, 
 hipError_t launch_rank_flags(const uint8_t* flags, int64_t n, int64_t n_new,
                              const int64_t* holes_before, const int64_t* movers_after,
                              int64_t* hole_at, int64_t* mover_at, int64_t* nmoves, hipStream_t s);
-// arr[hole_at[k]] = arr[mover_at[k]] for k < *nmoves (<= max_moves): elements
-// of `stride` bytes moved `word` bytes at a time (word divides stride and the
-// buffer's alignment; 1, 4, 8 or 16).
-hipError_t launch_move(void* arr, int64_t stride, int word, const int64_t* hole_at,
-                       const int64_t* mover_at, const int64_t* nmoves, int64_t max_moves,
-                       hipStream_t s);
+// Every array of a set moved by one launch: for k < *nmoves and every listed
+// array, element hole_at[k] <- element mover_at[k], `stride` bytes moved
+// `word` bytes at a time (word in {1, 4, 8, 16} divides stride and the
+// array's alignment).
+struct MoveArgs {
+  int32_t narrays;
+  char* base[kMaxArrays + 1];
+  int32_t stride[kMaxArrays + 1];
+  int32_t word[kMaxArrays + 1];
+};
+hipError_t launch_move_all(const MoveArgs& m, const int64_t* hole_at, const int64_t* mover_at,
+                           const int64_t* nmoves, int64_t max_moves, hipStream_t s);
 // p[0, bytes) = 0.
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
 

@@ -145,6 +145,12 @@ struct soax_set {
   XposeArgs xpose_host{};
   int block[3] = {0, 0, 0};
   int vec = 0;
+  // pinned host staging of the removal's tile counts and offsets, reused
+  // once the event says the last copy out of it has finished
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t pinned_done = nullptr;
+  bool pinned_pending = false;
 };
 
 struct soax_batch {
@@ -257,6 +263,9 @@ soax_status alloc_owned(const Layout& L, int64_t cap, void** soa_block, std::vec
 
 void free_set(soax_set* s) {
   if (!s) return;
+  if (s->pinned_pending) (void)hipEventSynchronize(s->pinned_done);
+  if (s->pinned_done) (void)hipEventDestroy(s->pinned_done);
+  if (s->pinned) (void)hipHostFree(s->pinned);
   if (s->xpose_dev) (void)hipFree(s->xpose_dev);
   if (s->owned_soa) (void)hipFree(s->owned_soa);
   if (s->owned_aos) (void)hipFree(s->owned_aos);
@@ -573,7 +582,8 @@ soax_status grow(soax_set* set, int64_t cap, hipStream_t s) {
   set->soa = nsoa;
   set->aos = static_cast<char*>(naos);
   set->cap = cap;
-  return SOAX_OK;
+  ++set->generation;
+  return finish_set(set);  // the stream is idle: the new table can be uploaded
 }
 
 // Room for `need` particles: bound sets must already have it; owned sets
@@ -586,13 +596,31 @@ soax_status ensure_capacity(soax_set* set, int64_t need, hipStream_t s) {
   return grow(set, std::max(need, std::min(2 * set->cap, kMaxParticles)), s);
 }
 
-// New size: bump the generation and refresh the transpose table once the
-// stream's earlier work (which may read the table) has finished.
-soax_status set_size(soax_set* set, int64_t n, hipStream_t s) {
-  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+// New size (host state only: the kernels take n as an argument).
+soax_status set_size(soax_set* set, int64_t n) {
   set->n = n;
+  set->xpose_host.n = n;
   ++set->generation;
-  return finish_set(set);
+  return SOAX_OK;
+}
+
+// Pinned host scratch of at least `bytes`, once its last use has finished.
+soax_status pinned_scratch(soax_set* set, size_t bytes, void** p) {
+  if (set->pinned_pending) {
+    HIP_TRY(hipEventSynchronize(set->pinned_done), "hipEventSynchronize");
+    set->pinned_pending = false;
+  }
+  if (!set->pinned_done)
+    HIP_TRY(hipEventCreateWithFlags(&set->pinned_done, hipEventDisableTiming), "hipEventCreate");
+  if (set->pinned_bytes < bytes) {
+    if (set->pinned) (void)hipHostFree(set->pinned);
+    set->pinned = nullptr;
+    set->pinned_bytes = 0;
+    HIP_TRY(hipHostMalloc(&set->pinned, bytes, hipHostMallocDefault), "hipHostMalloc");
+    set->pinned_bytes = bytes;
+  }
+  *p = set->pinned;
+  return SOAX_OK;
 }
 
 // Width in bytes of the moves of one AoS record: the widest of 16, 8, 4
@@ -634,8 +662,7 @@ soax_status soax_reserve(soax_set* set, int64_t capacity, void* stream) {
   if (!set->owns)
     return fail(SOAX_E_STATE, "a bound set holds at most %lld particles",
                 static_cast<long long>(set->cap));
-  if ((st = grow(set, capacity, s))) return st;
-  return set_size(set, set->n, s);
+  return grow(set, capacity, s);
 }
 
 soax_status soax_resize(soax_set* set, int64_t n, void* stream) {
@@ -656,7 +683,7 @@ soax_status soax_resize(soax_set* set, int64_t n, void* stream) {
       HIP_TRY(launch_zero(set->aos + set->n * set->L.stride, add * set->L.stride, s),
               "zero fill launch");
   }
-  return set_size(set, n, s);
+  return set_size(set, n);
 }
 
 soax_status soax_push_back(soax_set* set, const void* host_records, int64_t count, void* stream) {
@@ -705,7 +732,7 @@ soax_status soax_push_back(soax_set* set, const void* host_records, int64_t coun
     // the host records and the host table must outlive the copies
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   }
-  return set_size(set, n0 + count, s);
+  return set_size(set, n0 + count);
 }
 
 soax_status soax_rebind(soax_set* set, int64_t capacity, void* const* soa_ptrs, void* aos_ptr,
@@ -738,10 +765,12 @@ soax_status soax_rebind(soax_set* set, int64_t capacity, void* const* soa_ptrs, 
     if (aos_ptr)
       HIP_TRY(move(aos_ptr, set->aos, set->n * set->L.stride), "copy into the new buffers");
   }
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");  // copies done, old table unused
   if (soa_ptrs) set->soa.assign(soa_ptrs, soa_ptrs + set->L.narrays);
   set->aos = static_cast<char*>(aos_ptr);
   set->cap = capacity;
-  return set_size(set, set->n, s);
+  ++set->generation;
+  return finish_set(set);
 }
 
 soax_status soax_set_record(soax_set* set, int64_t i, const void* host_record) {
@@ -768,22 +797,27 @@ soax_status soax_remove_flagged(soax_set* set, const uint8_t* flags, int64_t* ne
   if (n == 0) return SOAX_OK;
   const hipStream_t s = as_stream(stream);
   const int64_t tiles = container_tiles(n);
-  std::vector<int32_t> counts(tiles);
+  // pinned staging: tile counts (int32), then the two offset tables (int64)
+  const size_t counts_bytes = (tiles * sizeof(int32_t) + 15) & ~size_t(15);
+  void* host = nullptr;
+  soax_status st;
+  if ((st = pinned_scratch(set, counts_bytes + 2 * tiles * sizeof(int64_t), &host))) return st;
+  int32_t* counts = static_cast<int32_t*>(host);
+  int64_t* tab = reinterpret_cast<int64_t*>(static_cast<char*>(host) + counts_bytes);
   DevBuf dcounts;
   HIP_TRY(dcounts.alloc(tiles * sizeof(int32_t), s), "hipMallocAsync(counts)");
   int32_t* dc = static_cast<int32_t*>(dcounts.p);
   HIP_TRY(launch_count_flags(flags, n, dc, s), "flag count launch");
-  HIP_TRY(hipMemcpyAsync(counts.data(), dc, tiles * sizeof(int32_t), hipMemcpyDeviceToHost, s),
+  HIP_TRY(hipMemcpyAsync(counts, dc, tiles * sizeof(int32_t), hipMemcpyDeviceToHost, s),
           "hipMemcpyAsync(counts)");
-  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");  // the one wait: n' is returned
   int64_t m = 0;
-  for (int32_t c : counts) m += c;
+  for (int64_t b = 0; b < tiles; ++b) m += counts[b];
   const int64_t n_new = n - m;
   const int64_t moves_max = std::min(m, n_new);
   if (moves_max > 0) {
-    // holes_before[b]: flagged in tiles < b; movers_after[b]: unflagged in tiles > b
+    // tab[b]: flagged in tiles < b; tab[tiles + b]: unflagged in tiles > b
     const int64_t T = container_tile_size();
-    std::vector<int64_t> tab(2 * tiles);
     int64_t acc = 0;
     for (int64_t b = 0; b < tiles; ++b) {
       tab[b] = acc;
@@ -794,32 +828,38 @@ soax_status soax_remove_flagged(soax_set* set, const uint8_t* flags, int64_t* ne
       tab[tiles + b] = acc;
       acc += std::min(T, n - b * T) - counts[b];
     }
+    MoveArgs mv{};
+    if (has_soa(set))
+      for (const Field& f : set->L.f)
+        for (int c = 0; c < f.dim; ++c) {
+          mv.base[mv.narrays] = static_cast<char*>(set->soa[f.first_array + c]);
+          mv.stride[mv.narrays] = f.es;
+          mv.word[mv.narrays] = f.es;
+          ++mv.narrays;
+        }
+    if (set->aos) {
+      mv.base[mv.narrays] = set->aos;
+      mv.stride[mv.narrays] = static_cast<int32_t>(set->L.stride);
+      mv.word[mv.narrays] = record_word(set);
+      ++mv.narrays;
+    }
     DevBuf dtab, dlists;
-    HIP_TRY(dtab.alloc(tab.size() * sizeof(int64_t), s), "hipMallocAsync(offsets)");
+    HIP_TRY(dtab.alloc(2 * tiles * sizeof(int64_t), s), "hipMallocAsync(offsets)");
     HIP_TRY(dlists.alloc((2 * moves_max + 1) * sizeof(int64_t), s), "hipMallocAsync(lists)");
     int64_t* dt = static_cast<int64_t*>(dtab.p);
     int64_t* hole_at = static_cast<int64_t*>(dlists.p);
     int64_t* mover_at = hole_at + moves_max;
     int64_t* nmoves = mover_at + moves_max;
-    HIP_TRY(hipMemcpyAsync(dt, tab.data(), tab.size() * sizeof(int64_t), hipMemcpyHostToDevice, s),
+    HIP_TRY(hipMemcpyAsync(dt, tab, 2 * tiles * sizeof(int64_t), hipMemcpyHostToDevice, s),
             "hipMemcpyAsync(offsets)");
+    HIP_TRY(hipEventRecord(set->pinned_done, s), "hipEventRecord");
+    set->pinned_pending = true;
     HIP_TRY(launch_rank_flags(flags, n, n_new, dt, dt + tiles, hole_at, mover_at, nmoves, s),
             "rank launch");
-    if (has_soa(set))
-      for (const Field& f : set->L.f)
-        for (int c = 0; c < f.dim; ++c)
-          HIP_TRY(launch_move(set->soa[f.first_array + c], f.es, f.es, hole_at, mover_at, nmoves,
-                              moves_max, s),
-                  "move launch");
-    if (set->aos)
-      HIP_TRY(launch_move(set->aos, set->L.stride, record_word(set), hole_at, mover_at, nmoves,
-                          moves_max, s),
-              "move launch");
-    // the host offset table must outlive its copy
-    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    HIP_TRY(launch_move_all(mv, hole_at, mover_at, nmoves, moves_max, s), "move launch");
   }
   *new_n = n_new;
-  return set_size(set, n_new, s);
+  return set_size(set, n_new);
 }
 
 // ----------------------------------------------------------- expressions
