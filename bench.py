@@ -300,7 +300,30 @@ def bench_adjoint(torch, soax, si, n, nsteps=200, k=20):
            "fwd": {"ms": tf.ms, "particle_steps_per_s": rate(n * nsteps, tf.ms)},
            "fwd_adjoint": {"ms": tb.ms, "particle_steps_per_s": rate(n * nsteps, tb.ms)},
            "loss": float(loss.item())}
-    del x0, target, xT, tape, lam, gx
+    del xT, tape, lam, gx
+    # the same with the positions kept inside 48-byte AoS records (pos at byte 8)
+    from paper_1710_03462_amd import autograd as A
+    stride, off = 48, 8
+    rec = torch.zeros((n, stride), dtype=torch.uint8, device="cuda")
+    rec[:, off:off + 24] = x0.t().contiguous().view(torch.uint8).view(n, 24)
+    rec = rec.view(-1)
+    out = torch.empty_like(rec)
+    lam_rec = torch.empty_like(rec)
+    gx_rec = torch.empty_like(rec)
+    A.forward_ckpt_records(rec, out, off, stride, n, abc, dt, nsteps, k)
+    with Timer(torch) as taf:
+        tape = A.forward_ckpt_records(rec, out, off, stride, n, abc, dt, nsteps, k)
+    del tape
+    with Timer(torch) as tab:
+        tape = A.forward_ckpt_records(rec, out, off, stride, n, abc, dt, nsteps, k)
+        loss_a = A.sqdist_loss_records(out, target, lam_rec, off, stride, n)
+        A.adjoint_records(tape, lam_rec, gx_rec, off, stride, n, abc, dt, nsteps, k)
+    res["fwd_aos"] = {"ms": taf.ms, "particle_steps_per_s": rate(n * nsteps, taf.ms)}
+    res["fwd_adjoint_aos"] = {"ms": tab.ms, "particle_steps_per_s": rate(n * nsteps, tab.ms)}
+    res["soa_over_aos_fwd"] = taf.ms / tf.ms
+    res["soa_over_aos_fwd_adjoint"] = tab.ms / tb.ms
+    res["aos_loss_equal"] = bool(float(loss_a.item()) == res["loss"])
+    del x0, target, rec, out, lam_rec, gx_rec, tape
     return res
 
 

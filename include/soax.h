@@ -344,6 +344,23 @@ soax_status soax_adjoint(const double* tape, const double* const* lamT, int64_t 
 soax_status soax_sqdist_loss(const double* const* xT, const double* const* target, int64_t n,
                              double* const* lamT, double* loss, void* stream);
 
+/* The same three calls with the position-like arrays (x0, xT, lamT,
+ * grad_x0) read and written at element i * stride (in doubles, 1..4096):
+ * stride 1 is the SoA form above; the record stride / 8 with pointers to a
+ * record's pos[d] keeps the positions inside AoS records (the AoS side of
+ * the SoA/AoS comparison for the adjoint).  target stays SoA; the tape is
+ * always [segment][3][n].  Results are bit-identical to the SoA form. */
+soax_status soax_rk2_forward_ckpt_strided(const double* const* x0, double* const* xT, int64_t n,
+                                          int64_t stride, const double* abc, double dt,
+                                          int64_t nsteps, int64_t k, double* tape, void* stream);
+soax_status soax_adjoint_strided(const double* tape, const double* const* lamT, int64_t n,
+                                 int64_t stride, const double* abc, double dt, int64_t nsteps,
+                                 int64_t k, double* const* grad_x0, double* grad_abc,
+                                 void* stream);
+soax_status soax_sqdist_loss_strided(const double* const* xT, int64_t stride,
+                                     const double* const* target, int64_t n, double* const* lamT,
+                                     double* loss, void* stream);
+
 /* --------------------------------------------------------------- batching */
 
 /*

@@ -98,6 +98,9 @@ def lib():
         "soax_eval": [vp, i32, vp, i32, vp],
         "soax_eval_ptrs": [i64, vp, i32, vp, vp, i32, vp, i32, vp],
         "soax_expr_source": [vp, i32, i32, vp, i32, vp, i64],
+        "soax_rk2_forward_ckpt_strided": [vp, vp, i64, i64, vp, dbl, i64, i64, vp, vp],
+        "soax_adjoint_strided": [vp, vp, i64, i64, vp, dbl, i64, i64, vp, vp, vp],
+        "soax_sqdist_loss_strided": [vp, i64, vp, i64, vp, vp, vp],
         "soax_copy": [vp, vp, i64, vp],
         "soax_strerror": [i32],
         "soax_last_error": [],

@@ -60,6 +60,54 @@ def sqdist_loss(xT, target, want_grad=True):
     return loss, lam
 
 
+# ---------------------------------------------------- positions in AoS records
+
+def _record_rows(buf, pos_offset, stride):
+    """Pointers to pos[0..2] of record 0 in a uint8 record buffer, and the
+    record stride in doubles."""
+    assert buf.dtype == torch.uint8 and buf.is_contiguous()
+    if pos_offset % 8 or stride % 8 or buf.data_ptr() % 8:
+        raise ValueError("positions inside records must be 8-byte aligned")
+    base = buf.data_ptr() + pos_offset
+    return (ctypes.c_void_p * 3)(base, base + 8, base + 16), stride // 8
+
+
+def forward_ckpt_records(x0_rec, xT_rec, pos_offset, stride, n, abc_host, dt, nsteps, k):
+    """The checkpointing forward with x0 and xT inside AoS records (uint8
+    buffers of n records; xT_rec may be x0_rec).  Returns the tape."""
+    r0, sd = _record_rows(x0_rec, pos_offset, stride)
+    rT, _ = _record_rows(xT_rec, pos_offset, stride)
+    nck = max(1, -(-int(nsteps) // int(k)))
+    tape = torch.empty((nck, 3, max(n, 1)), dtype=torch.float64, device=x0_rec.device)
+    check(lib().soax_rk2_forward_ckpt_strided(r0, rT, n, sd, abc_host, float(dt), int(nsteps),
+                                              int(k), ctypes.c_void_p(tape.data_ptr()),
+                                              current_stream()), "soax_rk2_forward_ckpt_strided")
+    return tape
+
+
+def sqdist_loss_records(xT_rec, target, lam_rec, pos_offset, stride, n):
+    """Loss with xT and the seed lam inside AoS records, target [3, n] SoA."""
+    rT, sd = _record_rows(xT_rec, pos_offset, stride)
+    rl, _ = _record_rows(lam_rec, pos_offset, stride)
+    loss = torch.empty(1, dtype=torch.float64, device=xT_rec.device)
+    check(lib().soax_sqdist_loss_strided(rT, sd, _rows(target), n, rl,
+                                         ctypes.c_void_p(loss.data_ptr()), current_stream()),
+          "soax_sqdist_loss_strided")
+    return loss
+
+
+def adjoint_records(tape, lam_rec, gx_rec, pos_offset, stride, n, abc_host, dt, nsteps, k):
+    """dL/d(A,B,C); dL/dx0 written into gx_rec's position slots."""
+    rl, sd = _record_rows(lam_rec, pos_offset, stride)
+    rg, _ = _record_rows(gx_rec, pos_offset, stride)
+    gabc = torch.empty(3, dtype=torch.float64, device=lam_rec.device)
+    check(lib().soax_adjoint_strided(ctypes.c_void_p(tape.data_ptr()), rl, n, sd, abc_host,
+                                     float(dt), int(nsteps), int(k), rg,
+                                     ctypes.c_void_p(gabc.data_ptr()), current_stream()),
+          "soax_adjoint_strided")
+    return gabc
+
+
 class RK2Advect(torch.autograd.Function):
     @staticmethod
     def forward(ctx, pos0, abc, dt, nsteps, k):

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const Abc p = to_abc(a.abc);
-  double x = a.x0[0][i], y = a.x0[1][i], z = a.x0[2][i];
+  const int64_t e = i * a.stride;
+  double x = a.x0[0][e], y = a.x0[1][e], z = a.x0[2][e];
   double* tp = a.tape + i;
   const int64_t n = a.n;
   int64_t until_ckpt = 0;
@@ -45,9 +46,9 @@ __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
     --until_ckpt;
     rk2_midpoint<SMALL>(p, a.dt, x, y, z);
   }
-  st1<true>(a.xT[0] + i, x);
-  st1<true>(a.xT[1] + i, y);
-  st1<true>(a.xT[2] + i, z);
+  st1<true>(a.xT[0] + e, x);
+  st1<true>(a.xT[1] + e, y);
+  st1<true>(a.xT[2] + e, z);
 }
 
 // Reverse one midpoint step taken from state (x, y, z).  With
@@ -117,7 +118,8 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
   double g0 = 0.0, g1 = 0.0, g2 = 0.0;
   if (i < a.n) {
     const int64_t n = a.n;
-    double l0 = a.lam[0][i], l1 = a.lam[1][i], l2 = a.lam[2][i];
+    const int64_t e = i * a.stride;
+    double l0 = a.lam[0][e], l1 = a.lam[1][e], l2 = a.lam[2][e];
     const int64_t nseg = (a.nsteps + a.k - 1) / a.k;
     for (int64_t c = nseg - 1; c >= 0; --c) {
       const int64_t len = min(a.k, a.nsteps - c * a.k);
@@ -143,9 +145,9 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
         }
       }
     }
-    a.gx[0][i] = l0;
-    a.gx[1][i] = l1;
-    a.gx[2][i] = l2;
+    a.gx[0][e] = l0;
+    a.gx[1][e] = l1;
+    a.gx[2][e] = l2;
   }
   block_sum3(g0, g1, g2, a.partial + 3 * static_cast<int64_t>(blockIdx.x));
 }
@@ -184,13 +186,14 @@ __global__ __launch_bounds__(kRedBlock) void sqdist_kernel(LossArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   double e0 = 0.0, e1 = 0.0, e2 = 0.0;
   if (i < a.n) {
-    e0 = a.xT[0][i] - a.target[0][i];
-    e1 = a.xT[1][i] - a.target[1][i];
-    e2 = a.xT[2][i] - a.target[2][i];
+    const int64_t e = i * a.stride;
+    e0 = a.xT[0][e] - a.target[0][i];
+    e1 = a.xT[1][e] - a.target[1][i];
+    e2 = a.xT[2][e] - a.target[2][i];
     if (a.lam[0]) {
-      a.lam[0][i] = 2.0 * e0;
-      a.lam[1][i] = 2.0 * e1;
-      a.lam[2][i] = 2.0 * e2;
+      a.lam[0][e] = 2.0 * e0;
+      a.lam[1][e] = 2.0 * e1;
+      a.lam[2][e] = 2.0 * e2;
     }
   }
   block_sum3(e0 * e0, e1 * e1, e2 * e2, a.partial + 3 * static_cast<int64_t>(blockIdx.x));

@@ -138,10 +138,14 @@ hipError_t launch_copy16(void* dst, const void* src, int64_t bytes, hipStream_t 
 
 // --------------------------------------------------------------- adjoint
 
+// Position-like arrays (x0, xT, lam, gx) are read at element i * stride:
+// stride 1 for SoA arrays, the record stride in doubles for positions kept
+// inside AoS records.  The tape is always [segment][3][n].
 struct CkptArgs {
   const double* x0[3];
   double* xT[3];
   double* tape;
+  int64_t stride;
   int64_t n;
   int64_t nsteps;
   int64_t k;
@@ -154,6 +158,7 @@ struct AdjointArgs {
   const double* tape;
   const double* lam[3];
   double* gx[3];
+  int64_t stride;
   double* partial;  // [nblocks][3] per-block parameter-gradient sums
   double* grad_abc;
   int64_t n;
@@ -168,8 +173,9 @@ hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s);
 
 struct LossArgs {
   const double* xT[3];
-  const double* target[3];
+  const double* target[3];  // SoA (stride 1)
   double* lam[3];
+  int64_t stride;           // of xT and lam
   double* partial;
   double* loss;
   int64_t n;

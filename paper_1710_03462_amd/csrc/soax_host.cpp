@@ -1021,10 +1021,16 @@ static soax_status check_rows(const void* const* rows, int64_t n, const char* wh
   return SOAX_OK;
 }
 
-soax_status soax_rk2_forward_ckpt(const double* const* x0, double* const* xT, int64_t n,
-                                  const double* abc, double dt, int64_t nsteps, int64_t k,
-                                  double* tape, void* stream) {
+static soax_status check_stride(int64_t stride) {
+  if (stride < 1 || stride > 4096) return fail(SOAX_E_ARG, "stride %lld outside 1..4096", static_cast<long long>(stride));
+  return SOAX_OK;
+}
+
+soax_status soax_rk2_forward_ckpt_strided(const double* const* x0, double* const* xT, int64_t n,
+                                          int64_t stride, const double* abc, double dt,
+                                          int64_t nsteps, int64_t k, double* tape, void* stream) {
   soax_status st;
+  if ((st = check_stride(stride))) return st;
   if ((st = check_rows(reinterpret_cast<const void* const*>(x0), n, "x0")) ||
       (st = check_rows(reinterpret_cast<const void* const*>(xT), n, "xT")) ||
       (st = check_abc_host(abc)))
@@ -1039,6 +1045,7 @@ soax_status soax_rk2_forward_ckpt(const double* const* x0, double* const* xT, in
     a.xT[d] = xT[d];
   }
   a.tape = tape;
+  a.stride = stride;
   a.n = n;
   a.nsteps = nsteps;
   a.k = k;
@@ -1048,10 +1055,18 @@ soax_status soax_rk2_forward_ckpt(const double* const* x0, double* const* xT, in
   return SOAX_OK;
 }
 
-soax_status soax_adjoint(const double* tape, const double* const* lamT, int64_t n,
-                         const double* abc, double dt, int64_t nsteps, int64_t k,
-                         double* const* grad_x0, double* grad_abc, void* stream) {
+soax_status soax_rk2_forward_ckpt(const double* const* x0, double* const* xT, int64_t n,
+                                  const double* abc, double dt, int64_t nsteps, int64_t k,
+                                  double* tape, void* stream) {
+  return soax_rk2_forward_ckpt_strided(x0, xT, n, 1, abc, dt, nsteps, k, tape, stream);
+}
+
+soax_status soax_adjoint_strided(const double* tape, const double* const* lamT, int64_t n,
+                                 int64_t stride, const double* abc, double dt, int64_t nsteps,
+                                 int64_t k, double* const* grad_x0, double* grad_abc,
+                                 void* stream) {
   soax_status st;
+  if ((st = check_stride(stride))) return st;
   if ((st = check_rows(reinterpret_cast<const void* const*>(lamT), n, "lamT")) ||
       (st = check_rows(reinterpret_cast<const void* const*>(grad_x0), n, "grad_x0")) ||
       (st = check_abc_host(abc)))
@@ -1074,6 +1089,7 @@ soax_status soax_adjoint(const double* tape, const double* const* lamT, int64_t 
   }
   a.partial = static_cast<double*>(partial);
   a.grad_abc = grad_abc;
+  a.stride = stride;
   a.n = n;
   a.nsteps = nsteps;
   a.k = k;
@@ -1086,8 +1102,32 @@ soax_status soax_adjoint(const double* tape, const double* const* lamT, int64_t 
   return SOAX_OK;
 }
 
+soax_status soax_adjoint(const double* tape, const double* const* lamT, int64_t n,
+                         const double* abc, double dt, int64_t nsteps, int64_t k,
+                         double* const* grad_x0, double* grad_abc, void* stream) {
+  return soax_adjoint_strided(tape, lamT, n, 1, abc, dt, nsteps, k, grad_x0, grad_abc, stream);
+}
+
+static soax_status sqdist_impl(const double* const* xT, int64_t stride,
+                               const double* const* target, int64_t n, double* const* lamT,
+                               double* loss, void* stream);
+
+soax_status soax_sqdist_loss_strided(const double* const* xT, int64_t stride,
+                                     const double* const* target, int64_t n, double* const* lamT,
+                                     double* loss, void* stream) {
+  soax_status st0;
+  if ((st0 = check_stride(stride))) return st0;
+  return sqdist_impl(xT, stride, target, n, lamT, loss, stream);
+}
+
 soax_status soax_sqdist_loss(const double* const* xT, const double* const* target, int64_t n,
                              double* const* lamT, double* loss, void* stream) {
+  return sqdist_impl(xT, 1, target, n, lamT, loss, stream);
+}
+
+static soax_status sqdist_impl(const double* const* xT, int64_t stride,
+                               const double* const* target, int64_t n, double* const* lamT,
+                               double* loss, void* stream) {
   soax_status st;
   if ((st = check_rows(reinterpret_cast<const void* const*>(xT), n, "xT")) ||
       (st = check_rows(reinterpret_cast<const void* const*>(target), n, "target")))
@@ -1108,6 +1148,7 @@ soax_status soax_sqdist_loss(const double* const* xT, const double* const* targe
   }
   a.partial = static_cast<double*>(partial);
   a.loss = loss;
+  a.stride = stride;
   a.n = n;
   e = launch_sqdist_loss(a, s);
   hipError_t e2 = hipFreeAsync(partial, s);

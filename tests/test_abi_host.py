@@ -36,7 +36,8 @@ def test_header_declarations_match_binding_signatures():
              "soax_batch_config", "soax_batch_get_config", "soax_batch_tune", "soax_copy",
              "soax_strerror", "soax_last_error", "soax_bind_capacity", "soax_capacity",
              "soax_reserve", "soax_resize", "soax_push_back", "soax_rebind", "soax_set_record",
-             "soax_remove_flagged", "soax_eval", "soax_eval_ptrs", "soax_expr_source"}
+             "soax_remove_flagged", "soax_eval", "soax_eval_ptrs", "soax_expr_source",
+             "soax_rk2_forward_ckpt_strided", "soax_adjoint_strided", "soax_sqdist_loss_strided"}
     assert declared == bound
 
 

@@ -128,3 +128,48 @@ def test_parameter_gradient_matches_gpu_finite_differences():
         fd = (gpu_fwd_bwd(x0, target, p, dt, nsteps, k)[2] -
               gpu_fwd_bwd(x0, target, m, dt, nsteps, k)[2]) / (2 * h)
         assert abs(fd - gabc[j]) <= 1e-6 * abs(gabc[j])
+
+
+def _records(x, stride, pos_offset, fill=0):
+    """uint8 record buffer (n records) with x [3, n] at pos_offset; other bytes `fill`."""
+    n = x.shape[1]
+    rec = torch.full((n, stride), fill, dtype=torch.uint8, device="cuda")
+    rec[:, pos_offset:pos_offset + 24] = x.t().contiguous().view(torch.uint8).view(n, 24)
+    return rec.view(-1)
+
+
+def _positions(rec, n, stride, pos_offset):
+    return rec.view(n, stride)[:, pos_offset:pos_offset + 24].contiguous().view(torch.float64).t()
+
+
+@pytest.mark.parametrize("stride,pos_offset", [(48, 8), (80, 16), (24, 0)])
+@pytest.mark.parametrize("n", [1, 1000])
+def test_positions_in_records_match_soa_bit_for_bit(ref, stride, pos_offset, n):
+    """Forward, loss and adjoint with the positions kept inside AoS records give
+    the SoA results bit for bit, and leave every other record byte alone."""
+    dt, nsteps, k = 5e-3, 60, 20
+    x0, target = si.adjoint_inputs(n, seed=n)
+    abc_host = soax.autograd._host3(torch.tensor(ABC, dtype=torch.float64))
+    X0, TG = gpu(x0), gpu(target)
+    xT, tape = soax.forward_ckpt(X0, abc_host, dt, nsteps, k)
+    loss, lam = soax.sqdist_loss(xT, TG)
+    gx, gabc = soax.adjoint(tape, lam, abc_host, dt, nsteps, k)
+    from paper_1710_03462_amd import autograd as A
+    rec = _records(X0, stride, pos_offset, fill=0xA5)
+    before = rec.clone()
+    tape_r = A.forward_ckpt_records(rec, rec, pos_offset, stride, n, abc_host, dt, nsteps, k)
+    lam_rec = torch.zeros(n * stride, dtype=torch.uint8, device="cuda")
+    loss_r = A.sqdist_loss_records(rec, TG, lam_rec, pos_offset, stride, n)
+    gx_rec = torch.zeros(n * stride, dtype=torch.uint8, device="cuda")
+    gabc_r = A.adjoint_records(tape_r, lam_rec, gx_rec, pos_offset, stride, n, abc_host, dt,
+                               nsteps, k)
+    torch.cuda.synchronize()
+    assert torch.equal(_positions(rec, n, stride, pos_offset), xT)
+    assert torch.equal(tape_r, tape)
+    assert torch.equal(loss_r, loss)
+    assert torch.equal(_positions(lam_rec, n, stride, pos_offset), lam)
+    assert torch.equal(_positions(gx_rec, n, stride, pos_offset), gx)
+    assert torch.equal(gabc_r, gabc)
+    r, b = rec.view(n, stride), before.view(n, stride)
+    assert torch.equal(r[:, :pos_offset], b[:, :pos_offset])
+    assert torch.equal(r[:, pos_offset + 24:], b[:, pos_offset + 24:])
