@@ -79,7 +79,11 @@ def _same(a, b):
 
 
 def as_expr(x):
-    return x if isinstance(x, Expr) else Expr([(CONST, None, float(x))])
+    if isinstance(x, Expr):
+        return x
+    if isinstance(x, torch.Tensor):
+        raise TypeError("wrap a tensor with array() to use it in an expression")
+    return Expr([(CONST, None, float(x))])
 
 
 def sqrt(e):

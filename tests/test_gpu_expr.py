@@ -114,7 +114,8 @@ def test_streaming_size_sampled():
     a = torch.randn(n, generator=g, dtype=torch.float64, device="cuda")
     b = torch.rand(n, generator=g, dtype=torch.float64, device="cuda") + 0.5
     out = torch.empty_like(a)
-    soax.evaluate(out, E.sqrt(a * a + b) / b)
+    A, B = E.array(a), E.array(b)
+    soax.evaluate(out, E.sqrt(A * A + B) / B)
     torch.cuda.synchronize()
     idx = np.concatenate([np.arange(0, 1000), np.arange(n - 1000, n),
                           np.random.default_rng(0).integers(0, n, 5000)])
