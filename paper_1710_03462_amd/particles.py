@@ -19,6 +19,9 @@ NUMPY_DTYPE = {"i8": np.int8, "u8": np.uint8, "i32": np.int32, "i64": np.int64,
                "f32": np.float32, "f64": np.float64}
 
 
+MAX_PARTICLES = 2 ** 31 - 1  # records a set can hold (the C ABI's limit)
+
+
 def current_stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -87,7 +90,7 @@ class ParticleSet:
     # --------------------------------------------------------------- storage
     def _alloc(self, cap):
         ld = max(self.pad, -(-cap // self.pad) * self.pad)
-        self.capacity = ld  # the buffers' whole length is usable
+        self.capacity = min(ld, MAX_PARTICLES)  # the buffers' whole length, up to the limit
         self._soa_store = [torch.empty(ld, dtype=TORCH_DTYPE[t], device=self.device)
                            for _, _, t in self.schema.arrays()] if self._has_soa else None
         self._aos_store = torch.zeros(max(ld * self.stride, 16), dtype=torch.uint8,
@@ -112,7 +115,7 @@ class ParticleSet:
         if need <= self.capacity:
             return
         old = (self._soa_store, self._aos_store)
-        self._alloc(max(need, 2 * self.capacity))
+        self._alloc(min(max(need, 2 * self.capacity), MAX_PARTICLES))
         check(lib().soax_rebind(self.handle, self.capacity, self._soa_ptrs(), self._aos_ptr(),
                                 current_stream()), "soax_rebind")
         del old  # the library has copied the particles and synchronised

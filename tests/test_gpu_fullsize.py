@@ -235,3 +235,33 @@ def test_config4_batch_256_sets(ref):
                 assert_positions_close(got[1 + d], want[1 + d])
                 assert_fields_close(got[4 + d], want[4 + d])
     b.close()
+
+
+def test_maximum_particle_count_soa(ref):
+    """n = 2^31 - 1, the library's limit (86 GB of SoA arrays): the fill, an
+    Euler step and an RK2 step index past 2^31 elements and 2^34 bytes; the
+    first and last particles are compared with the oracle."""
+    n = 2 ** 31 - 1
+    fields = si.BASE_FIELDS
+    sch = ref.Schema(fields)
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 100 * 2 ** 30:
+        pytest.skip("needs about 90 GB of free device memory")
+    ps = soax.ParticleSet(fields, n, aos=False)
+    ps.fill(seed=3)
+    ps.step("soa", "euler", 1e-3, 1, wrap=True)
+    ps.step("soa", "rk2_abc", 1e-3, 1, abc=[1.0, 1.0, 1.0], wrap=True)
+    torch.cuda.synchronize()
+    for r0, cnt in [(0, 64), (2 ** 31 - 4096, 4096 - 1), (n - 64, 64)]:
+        want = ref.fill_range(sch, r0, cnt, seed=3)
+        got0 = gpu_slice(ps, r0, cnt)
+        assert np.array_equal(got0[0], np.arange(r0, r0 + cnt, dtype=np.int32))
+        ref.step_soa(sch, want, ref.EULER, 1e-3, 1, wrap=True)
+        ref.step_soa(sch, want, ref.RK2_ABC, 1e-3, 1, abc=[1.0, 1.0, 1.0], wrap=True)
+        for d in range(3):
+            assert_positions_close(got0[1 + d], want[1 + d])
+            assert_fields_close(got0[4 + d], want[4 + d])
+    ps.close()
+    del ps
+    torch.cuda.empty_cache()
