@@ -109,6 +109,28 @@ def bench_integrators(torch, soax, ps, n, nsteps=10):
     return out
 
 
+def bench_aosoa(torch, soax, si, n, nsteps=20):
+    """The tiled (AoSoA, 64-particle tiles) copy of the headline set: Euler and
+    RK2 steps timed like the SoA rows (60 B per particle-step algorithmic)."""
+    ps = soax.ParticleSet(si.BASE_FIELDS, n, aos=False, aosoa=True)
+    ps.fill(seed=0, vel_mode=1, abc=[1, 1, 1])
+    ps.soa_to_aosoa()
+    out = {}
+    for integ, steps in (("euler", nsteps), ("rk2_abc", nsteps)):
+        ps.step("aosoa", integ, 1e-3, 2, abc=[1, 1, 1], wrap=True)
+        with Timer(torch) as t:
+            ps.step("aosoa", integ, 1e-3, steps, abc=[1, 1, 1], wrap=True)
+        per = t.ms / steps
+        out[integ] = {"updates_per_s": rate(n * steps, t.ms), "ms_per_launch": per,
+                      "alg_GBps": gbs(60 * n, per)}
+    with Timer(torch) as t:
+        ps.soa_to_aosoa()
+    out["soa_to_aosoa"] = {"ms": t.ms, "GBps": gbs(2 * ps.soa_bytes * n, t.ms)}
+    ps.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_euler(torch, soax, ps, n, nsteps, layout):
     ps.step(layout, "euler", 1e-3, 2, wrap=True)
     with Timer(torch) as t:
@@ -440,7 +462,7 @@ def main():
     ap.add_argument("--n", type=float, default=1e8, help="particles of the headline workload")
     ap.add_argument("--rows", default="all",
                     help="comma list of extra rows: aos,euler,small,copy,wide,adjoint,batch,"
-                         "remove,expr,integrators | all | none")
+                         "remove,expr,integrators,aosoa | all | none")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--sweep", action="store_true",
                     help="run only the N x SIZE sweep of the paper's GPU experiment and print "
@@ -468,7 +490,7 @@ def main():
                           "device": torch.cuda.get_device_name(0)}), flush=True)
         return 0
     rows = {"aos", "euler", "small", "copy", "wide", "adjoint", "batch", "remove", "expr",
-            "integrators"} \
+            "integrators", "aosoa"} \
         if args.rows == "all" else \
         set() if args.rows == "none" else set(args.rows.split(","))
     n = int(args.n)
@@ -516,6 +538,9 @@ def main():
     ps.close()
     del ps
     torch.cuda.empty_cache()
+    if "aosoa" in rows:
+        log("[bench] tiled (AoSoA) copy of the headline set")
+        out_rows["aosoa"] = bench_aosoa(torch, soax, si, n)
     if "small" in rows:
         log("[bench] 1e5-particle Euler workload")
         out_rows["euler_1e5"] = bench_small_euler(torch, soax, si)

@@ -62,7 +62,8 @@ typedef struct {
   int32_t packed;
 } soax_schema;
 
-typedef enum { SOAX_SOA = 0, SOAX_AOS = 1, SOAX_AOS_NAIVE = 2 } soax_layout;
+/* SOAX_AOSOA: the optional tiled copy (see soax_bind_aosoa). */
+typedef enum { SOAX_SOA = 0, SOAX_AOS = 1, SOAX_AOS_NAIVE = 2, SOAX_AOSOA = 3 } soax_layout;
 
 /*
  * Integrators.  Properties are found by name: "pos" (dim 3, f32 or f64),
@@ -152,7 +153,8 @@ soax_status soax_layout_info(const soax_set* set, int64_t* field_offsets, int64_
                              int64_t* soa_bytes);
 
 /* Device pointers of the set's buffers: array `index` of the SoA copy (see
- * soax_bind for the numbering) or, with index = -1, the AoS buffer. */
+ * soax_bind for the numbering), with index = -1 the AoS buffer, with
+ * index = -2 the AoSoA buffer (NULL when none is bound). */
 soax_status soax_buffer(const soax_set* set, int32_t index, void** ptr);
 
 /*
@@ -171,7 +173,8 @@ soax_status soax_fill(soax_set* set, uint64_t seed, int32_t vel_mode, const soax
  * nsteps time steps of `integrator` on one layout: SOAX_SOA (vector loads
  * per array), SOAX_AOS (records staged through LDS with coalesced 16-byte
  * accesses), SOAX_AOS_NAIVE (one thread per record, direct per-field
- * accesses, the uncoalesced pattern of Section 3.2).  Only pos/vel are
+ * accesses, the uncoalesced pattern of Section 3.2), SOAX_AOSOA (the tiled
+ * copy, one thread per particle).  Only pos/vel are
  * written; every other byte keeps its value.  params may be NULL for Euler
  * steps without wrap.  Errors: ARG, SCHEMA, LAYOUT, HIP.
  */
@@ -190,9 +193,39 @@ soax_status soax_step_config(soax_set* set, int32_t layout, int32_t block, int32
 soax_status soax_aos_to_soa(soax_set* set, void* stream);
 soax_status soax_soa_to_aos(soax_set* set, void* stream);
 
-/* Copy record i of one layout (SOAX_SOA or SOAX_AOS) to host memory in AoS
- * form (stride bytes, padding 0).  Synchronises the null stream. */
+/* Copy record i of one layout (SOAX_SOA, SOAX_AOS or SOAX_AOSOA) to host
+ * memory in AoS form (stride bytes, padding 0).  Synchronises the null stream. */
 soax_status soax_get_record(const soax_set* set, int32_t layout, int64_t i, void* host_record);
+
+/* ----------------------------------------------------------- AoSoA tiles */
+
+/*
+ * An optional third copy in a tiled layout (array of structures of arrays):
+ * particles in tiles of 64 (one wavefront); a tile holds, for every SoA array
+ * in order, its 64 elements back to back, so element i of array a is at byte
+ *   (i / 64) * tile_bytes + array_offsets[a] + (i % 64) * element_size(a),
+ * array_offsets[a] = 64 * (element sizes of the arrays before a), tile_bytes
+ * = 64 * (sum of all element sizes).  The layout keeps a particle's fields in
+ * one few-KB block (like an AoS record) while a wavefront still reads each
+ * field as one contiguous run (like SoA).  Not a layout of the paper's
+ * benchmark; a variant for comparison.
+ */
+
+/* Host only: the tile layout of a schema (array_offsets[narrays] may be NULL). */
+soax_status soax_aosoa_layout(const soax_schema* schema, int64_t* array_offsets,
+                              int64_t* tile_bytes);
+
+/* Attach a caller-owned, 16-byte aligned buffer of at least
+ * ceil(capacity / 64) * tile_bytes bytes as the set's AoSoA copy (NULL
+ * detaches); needs the SoA copy.  Contents are undefined until converted.
+ * Container calls do not update the AoSoA copy; growth past the capacity and
+ * soax_rebind detach it.  Errors: ARG (too small), LAYOUT, OOM, HIP. */
+soax_status soax_bind_aosoa(soax_set* set, void* aosoa, int64_t bytes);
+
+/* Conversions between the SoA and AoSoA copies, byte-exact; soa -> aosoa
+ * writes the unused lanes of the last tile as zero bytes. */
+soax_status soax_soa_to_aosoa(soax_set* set, void* stream);
+soax_status soax_aosoa_to_soa(soax_set* set, void* stream);
 
 /* ------------------------------------------------------------ containers */
 

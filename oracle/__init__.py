@@ -57,6 +57,9 @@ def lib():
         L.soaxref_step_aos.argtypes = [sp, i64, vp, i32, dbl, i64, vp, i32]
         L.soaxref_aos_to_soa.argtypes = [sp, i64, vp, vp]
         L.soaxref_soa_to_aos.argtypes = [sp, i64, vp, vp]
+        L.soaxref_aosoa_layout.argtypes = [sp, vp, vp]
+        L.soaxref_soa_to_aosoa.argtypes = [sp, i64, vp, vp]
+        L.soaxref_aosoa_to_soa.argtypes = [sp, i64, vp, vp]
         L.soaxref_rk2_forward.argtypes = [i64, vp, vp, vp, dbl, i64, vp]
         L.soaxref_sqdist_loss.argtypes = [i64, vp, vp, vp]
         L.soaxref_sqdist_loss.restype = dbl
@@ -255,6 +258,34 @@ def soa_to_aos(schema, arrays):
     _check(lib().soaxref_soa_to_aos(schema.ref, n, _ptrs(arrays), aos.ctypes.data),
            "soaxref_soa_to_aos")
     return aos
+
+
+AOSOA_W = 64
+
+
+def aosoa_layout(schema):
+    """(byte offset of every SoA array inside a tile, tile bytes)."""
+    narr = sum(d for _, _, d in schema.fields)
+    off = (ctypes.c_int64 * max(narr, 1))()
+    tile = ctypes.c_int64()
+    _check(lib().soaxref_aosoa_layout(schema.ref, off, ctypes.byref(tile)), "soaxref_aosoa_layout")
+    return list(off)[:narr], tile.value
+
+
+def soa_to_aosoa(schema, arrays):
+    n = len(arrays[0]) if arrays else 0
+    _, tile = aosoa_layout(schema)
+    out = np.full(-(-n // AOSOA_W) * tile, 0xA5, dtype=np.uint8)
+    _check(lib().soaxref_soa_to_aosoa(schema.ref, n, _ptrs(arrays), out.ctypes.data),
+           "soaxref_soa_to_aosoa")
+    return out
+
+
+def aosoa_to_soa(schema, buf, n):
+    arrays = empty_soa(schema, n)
+    _check(lib().soaxref_aosoa_to_soa(schema.ref, n, buf.ctypes.data, _ptrs(arrays)),
+           "soaxref_aosoa_to_soa")
+    return arrays
 
 
 def rk2_forward(x0, abc, dt, nsteps, store_states=False):

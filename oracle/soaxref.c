@@ -356,6 +356,61 @@ int soaxref_soa_to_aos(const ref_schema* s, int64_t n, void* const* soa, void* a
   return 0;
 }
 
+/* -------------------------------------------------------------- AoSoA tiles */
+
+int soaxref_aosoa_layout(const ref_schema* s, int64_t* array_offsets, int64_t* tile_bytes) {
+  int rc = check_schema(s);
+  if (rc) return rc;
+  int64_t acc = 0;
+  for (int f = 0; f < s->nfields; ++f) {
+    int a = first_array(s, f);
+    for (int c = 0; c < s->dims[f]; ++c) {
+      if (array_offsets) array_offsets[a + c] = REF_AOSOA_W * acc;
+      acc += esize(s->dtypes[f]);
+    }
+  }
+  if (tile_bytes) *tile_bytes = REF_AOSOA_W * acc;
+  return 0;
+}
+
+int soaxref_soa_to_aosoa(const ref_schema* s, int64_t n, void* const* soa, void* aosoa) {
+  int64_t aoff[3 * 64], tile;
+  int rc = check_schema(s);
+  if (rc) return rc;
+  if (n < 0 || !soa || (!aosoa && n > 0)) return -1;
+  soaxref_aosoa_layout(s, aoff, &tile);
+  const int64_t ntiles = (n + REF_AOSOA_W - 1) / REF_AOSOA_W;
+  memset(aosoa, 0, (size_t)(ntiles * tile));
+  for (int64_t i = 0; i < n; ++i) {
+    char* t = (char*)aosoa + (i / REF_AOSOA_W) * tile;
+    for (int f = 0; f < s->nfields; ++f) {
+      int64_t es = esize(s->dtypes[f]);
+      int a = first_array(s, f);
+      for (int c = 0; c < s->dims[f]; ++c)
+        memcpy(t + aoff[a + c] + (i % REF_AOSOA_W) * es, (const char*)soa[a + c] + i * es, es);
+    }
+  }
+  return 0;
+}
+
+int soaxref_aosoa_to_soa(const ref_schema* s, int64_t n, const void* aosoa, void* const* soa) {
+  int64_t aoff[3 * 64], tile;
+  int rc = check_schema(s);
+  if (rc) return rc;
+  if (n < 0 || !soa || (!aosoa && n > 0)) return -1;
+  soaxref_aosoa_layout(s, aoff, &tile);
+  for (int64_t i = 0; i < n; ++i) {
+    const char* t = (const char*)aosoa + (i / REF_AOSOA_W) * tile;
+    for (int f = 0; f < s->nfields; ++f) {
+      int64_t es = esize(s->dtypes[f]);
+      int a = first_array(s, f);
+      for (int c = 0; c < s->dims[f]; ++c)
+        memcpy((char*)soa[a + c] + i * es, t + aoff[a + c] + (i % REF_AOSOA_W) * es, es);
+    }
+  }
+  return 0;
+}
+
 /* ------------------------------------------------------------- containers */
 
 /*

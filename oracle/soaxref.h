@@ -89,6 +89,19 @@ int64_t soaxref_remove_flagged(const ref_schema* s, int64_t n, void* const* soa,
 int soaxref_aos_to_soa(const ref_schema* s, int64_t n, const void* aos, void* const* soa);
 int soaxref_soa_to_aos(const ref_schema* s, int64_t n, void* const* soa, void* aos);
 
+/* AoSoA (tiled) layout: particles grouped in tiles of REF_AOSOA_W; a tile
+ * holds, for every SoA array in order, its REF_AOSOA_W elements back to
+ * back, so element i of array a is at byte
+ *   (i / W) * tile_bytes + array_offsets[a] + (i % W) * esize(a),
+ *   array_offsets[a] = W * (sum of the element sizes of the arrays before a),
+ *   tile_bytes = W * (sum of all element sizes).
+ * soa_to_aosoa writes ceil(n / W) whole tiles, the unused lanes of the last
+ * tile as zero bytes. */
+enum { REF_AOSOA_W = 64 };
+int soaxref_aosoa_layout(const ref_schema* s, int64_t* array_offsets, int64_t* tile_bytes);
+int soaxref_soa_to_aosoa(const ref_schema* s, int64_t n, void* const* soa, void* aosoa);
+int soaxref_aosoa_to_soa(const ref_schema* s, int64_t n, const void* aosoa, void* const* soa);
+
 /*
  * RK2 (explicit midpoint) advection without wrap, positions only:
  * x[d][i] in, xT[d][i] out.  states, if not NULL, receives every state

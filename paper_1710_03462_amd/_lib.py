@@ -15,8 +15,8 @@ SOAX_OK = 0
 STATUS = {-1: "SOAX_E_ARG", -2: "SOAX_E_SCHEMA", -3: "SOAX_E_RANGE", -4: "SOAX_E_LAYOUT",
           -5: "SOAX_E_OOM", -6: "SOAX_E_HIP", -7: "SOAX_E_STATE"}
 DTYPE = {"i8": 1, "u8": 2, "i32": 3, "i64": 4, "f32": 5, "f64": 6}
-SOA, AOS, AOS_NAIVE = 0, 1, 2
-LAYOUTS = {"soa": SOA, "aos": AOS, "aos_naive": AOS_NAIVE}
+SOA, AOS, AOS_NAIVE, AOSOA = 0, 1, 2, 3
+LAYOUTS = {"soa": SOA, "aos": AOS, "aos_naive": AOS_NAIVE, "aosoa": AOSOA}
 EULER, EULER_ACC, RK2_ABC, HEUN_ABC, RK4_ABC, SYMPLECTIC_EULER = 0, 1, 2, 3, 4, 5
 INTEGRATORS = {"euler": EULER, "euler_acc": EULER_ACC, "rk2_abc": RK2_ABC, "heun_abc": HEUN_ABC,
                "rk4_abc": RK4_ABC, "symplectic_euler": SYMPLECTIC_EULER}
@@ -101,6 +101,10 @@ def lib():
         "soax_rk2_forward_ckpt_strided": [vp, vp, i64, i64, vp, dbl, i64, i64, vp, vp],
         "soax_adjoint_strided": [vp, vp, i64, i64, vp, dbl, i64, i64, vp, vp, vp],
         "soax_sqdist_loss_strided": [vp, i64, vp, i64, vp, vp, vp],
+        "soax_aosoa_layout": [sp, vp, vp],
+        "soax_bind_aosoa": [vp, vp, i64],
+        "soax_soa_to_aosoa": [vp, vp],
+        "soax_aosoa_to_soa": [vp, vp],
         "soax_copy": [vp, vp, i64, vp],
         "soax_strerror": [i32],
         "soax_last_error": [],

@@ -437,6 +437,105 @@ __global__ __launch_bounds__(256) void soa_to_aos_kernel(const XposeArgs* __rest
   stage_out<STREAM>(t.aos + r0 * stride, lds, nbytes);
 }
 
+// ------------------------------------------------------------ AoSoA tiles
+
+// Element i of the array at offset `off` inside each tile.
+template <typename T>
+__device__ __forceinline__ T* tile_elem(char* base, int64_t tile_bytes, int32_t off, int64_t i) {
+  return reinterpret_cast<T*>(base + (i / kAosoaW) * tile_bytes + off) + (i % kAosoaW);
+}
+
+// SoA <-> AoSoA: one thread per particle lane; the 64 lanes of a wave cover
+// one tile, so both sides of every copy are contiguous runs.
+template <bool TO_SOA>
+__global__ __launch_bounds__(256) void aosoa_xpose_kernel(const XposeArgs* __restrict__ tp,
+                                                          int64_t n) {
+  const XposeArgs& t = *tp;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t lanes = (n + kAosoaW - 1) / kAosoaW * kAosoaW;
+  if (i >= lanes) return;
+  char* tile = t.aos + (i / kAosoaW) * t.stride;
+  const int lane = static_cast<int>(i % kAosoaW);
+  const int na = t.narrays;
+  for (int a = 0; a < na; ++a) {
+    const int es = t.es[a];
+    char* e = tile + t.off[a] + lane * es;
+    if (i < n) {
+      if constexpr (TO_SOA) copy_elem<true>(t.soa[a] + i * es, e, es);
+      else copy_elem<true>(e, t.soa[a] + i * es, es);
+    } else if constexpr (!TO_SOA) {
+      for (int b = 0; b < es; ++b) e[b] = 0;
+    }
+  }
+}
+
+template <int INTEG, typename PT, typename VT, bool SMALL, bool STREAM>
+__global__ __launch_bounds__(1024) void aosoa_step_kernel(AosoaStepArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const Abc p = to_abc(a.abc);
+  PT* P[3];
+  VT* V[3];
+  VT* G[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    P[d] = tile_elem<PT>(a.base, a.tile_bytes, a.off_pos[d], i);
+    V[d] = tile_elem<VT>(a.base, a.tile_bytes, a.off_vel[d], i);
+    G[d] = tile_elem<VT>(a.base, a.tile_bytes, a.off_acc[d], i);
+  }
+  if constexpr (!field_integrator(INTEG)) {
+    // one component at a time, as in the SoA kernel
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      PT x = ld1<false>(P[d]);
+      VT v = ld1<STREAM && INTEG == kEuler>(V[d]);
+      const VT g = uses_acc(INTEG) ? ld1<STREAM>(G[d]) : VT(0);
+      euler_component<INTEG, PT, VT>(x, v, g, a.dt, a.wrap);
+      st1<STREAM>(P[d], x);
+      if constexpr (uses_acc(INTEG)) st1<STREAM>(V[d], v);
+    }
+  } else {
+    PT x = ld1<false>(P[0]), y = ld1<false>(P[1]), z = ld1<false>(P[2]);
+    VT u = VT(0), v = VT(0), w = VT(0);
+    update_particle<INTEG, PT, VT, SMALL>(x, y, z, u, v, w, VT(0), VT(0), VT(0), a.dt, p, a.wrap);
+    st1<STREAM>(P[0], x);
+    st1<STREAM>(P[1], y);
+    st1<STREAM>(P[2], z);
+    st1<STREAM>(V[0], u);
+    st1<STREAM>(V[1], v);
+    st1<STREAM>(V[2], w);
+  }
+}
+
+template <int INTEG, typename PT, typename VT>
+hipError_t aosoa_step_t(int block, const AosoaStepArgs& a, hipStream_t s) {
+  const int64_t grid = (a.n + block - 1) / block;
+  int64_t bytes = 3 * (sizeof(PT) + sizeof(VT));
+  if (uses_acc(INTEG)) bytes += 3 * sizeof(VT);
+  const bool stream = a.n * bytes >= kStreamBytes;
+  bool small = false;
+  if constexpr (field_integrator(INTEG)) small = small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C);
+#define SOAX_AOSOA(SM, ST) \
+  hipLaunchKernelGGL((aosoa_step_kernel<INTEG, PT, VT, SM, ST>), dim3(grid), dim3(block), 0, s, a)
+  if (small && stream) SOAX_AOSOA(true, true);
+  else if (small) SOAX_AOSOA(true, false);
+  else if (stream) SOAX_AOSOA(false, true);
+  else SOAX_AOSOA(false, false);
+#undef SOAX_AOSOA
+  return hipGetLastError();
+}
+
+template <int INTEG>
+hipError_t aosoa_dispatch(int pos_t, int vel_t, int block, const AosoaStepArgs& a, hipStream_t s) {
+  if (pos_t == kF64 && vel_t == kF32) return aosoa_step_t<INTEG, double, float>(block, a, s);
+  if (pos_t == kF64 && vel_t == kF64) return aosoa_step_t<INTEG, double, double>(block, a, s);
+  if constexpr (!field_integrator(INTEG)) {
+    if (pos_t == kF32 && vel_t == kF32) return aosoa_step_t<INTEG, float, float>(block, a, s);
+    if (pos_t == kF32 && vel_t == kF64) return aosoa_step_t<INTEG, float, double>(block, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 // ------------------------------------------------------------------- fill
 
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
@@ -625,6 +724,32 @@ hipError_t launch_xpose(bool to_soa, const XposeArgs& host, const XposeArgs* dev
   }
 #undef SOAX_XPOSE
   return hipGetLastError();
+}
+
+hipError_t launch_aosoa_xpose(bool to_soa, const XposeArgs& host, const XposeArgs* dev,
+                              hipStream_t s) {
+  if (host.n == 0) return hipSuccess;
+  const int64_t lanes = (host.n + kAosoaW - 1) / kAosoaW * kAosoaW;
+  const int64_t grid = (lanes + 255) / 256;
+  if (to_soa)
+    hipLaunchKernelGGL(aosoa_xpose_kernel<true>, dim3(grid), dim3(256), 0, s, dev, host.n);
+  else
+    hipLaunchKernelGGL(aosoa_xpose_kernel<false>, dim3(grid), dim3(256), 0, s, dev, host.n);
+  return hipGetLastError();
+}
+
+hipError_t launch_aosoa_step(int integ, int pos_t, int vel_t, int block, const AosoaStepArgs& a,
+                             hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  switch (integ) {
+    case kEuler: return aosoa_dispatch<kEuler>(pos_t, vel_t, block, a, s);
+    case kEulerAcc: return aosoa_dispatch<kEulerAcc>(pos_t, vel_t, block, a, s);
+    case kRk2Abc: return aosoa_dispatch<kRk2Abc>(pos_t, vel_t, block, a, s);
+    case kHeunAbc: return aosoa_dispatch<kHeunAbc>(pos_t, vel_t, block, a, s);
+    case kRk4Abc: return aosoa_dispatch<kRk4Abc>(pos_t, vel_t, block, a, s);
+    case kSymEuler: return aosoa_dispatch<kSymEuler>(pos_t, vel_t, block, a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_fill(const FillArgs& a, hipStream_t s) {

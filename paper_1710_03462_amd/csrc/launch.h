@@ -107,6 +107,29 @@ struct XposeArgs {
 // memory, uploaded when the set's buffers change); host.n is passed by value.
 hipError_t launch_xpose(bool to_soa, const XposeArgs& host, const XposeArgs* dev, hipStream_t s);
 
+// AoSoA tiles of kAosoaW particles: a tile holds every SoA array's kAosoaW
+// elements back to back.  The conversions use an XposeArgs table with
+// aos = the tiled buffer, stride = bytes per tile and off[a] = the offset of
+// array a inside a tile; soa -> aosoa writes the unused lanes of the last
+// tile as zero bytes.
+constexpr int kAosoaW = 64;
+hipError_t launch_aosoa_xpose(bool to_soa, const XposeArgs& host, const XposeArgs* dev,
+                              hipStream_t s);
+
+struct AosoaStepArgs {
+  char* base;          // tiled buffer
+  int64_t tile_bytes;
+  int32_t off_pos[3];  // offsets of the component arrays inside a tile
+  int32_t off_vel[3];
+  int32_t off_acc[3];
+  int64_t n;
+  double dt;
+  AbcParams abc;
+  int32_t wrap;
+};
+hipError_t launch_aosoa_step(int integ, int pos_t, int vel_t, int block, const AosoaStepArgs& a,
+                             hipStream_t s);
+
 // -------------------------------------------------------------------- fill
 
 enum FillRule : int32_t {

@@ -143,8 +143,13 @@ struct soax_set {
   bool aos_base_ok = false;   // AoS buffer 16-byte aligned
   XposeArgs* xpose_dev = nullptr;
   XposeArgs xpose_host{};
-  int block[3] = {0, 0, 0};
+  int block[4] = {0, 0, 0, 0};
   int vec = 0;
+  // optional AoSoA copy (caller-owned buffer) and its conversion table
+  char* aosoa = nullptr;
+  int64_t aosoa_bytes = 0;
+  XposeArgs* aosoa_dev = nullptr;
+  XposeArgs aosoa_host{};
   // pinned host staging of the removal's tile counts and offsets, reused
   // once the event says the last copy out of it has finished
   void* pinned = nullptr;
@@ -192,6 +197,22 @@ soax_status check_n(const Layout& L, int64_t n) {
 // room for no particle); a bound set has the copies it was given.
 bool has_soa(const soax_set* s) { return !s->soa.empty(); }
 bool has_aos(const soax_set* s) { return s->owns || s->aos != nullptr; }
+
+// AoSoA: byte offset of every SoA array inside a tile, and bytes per tile.
+int64_t aosoa_tile(const Layout& L, std::vector<int32_t>* off) {
+  int64_t acc = 0;
+  if (off) off->assign(L.narrays, 0);
+  for (const Field& f : L.f)
+    for (int c = 0; c < f.dim; ++c) {
+      if (off) (*off)[f.first_array + c] = static_cast<int32_t>(kAosoaW * acc);
+      acc += f.es;
+    }
+  return kAosoaW * acc;
+}
+
+int64_t aosoa_need(const Layout& L, int64_t cap) {
+  return (cap + kAosoaW - 1) / kAosoaW * aosoa_tile(L, nullptr);
+}
 
 // Fill the transpose table from the set's buffers and size, and upload it
 // (synchronous copy; callers order it after earlier work that reads it).
@@ -263,6 +284,7 @@ soax_status alloc_owned(const Layout& L, int64_t cap, void** soa_block, std::vec
 
 void free_set(soax_set* s) {
   if (!s) return;
+  if (s->aosoa_dev) (void)hipFree(s->aosoa_dev);
   if (s->pinned_pending) (void)hipEventSynchronize(s->pinned_done);
   if (s->pinned_done) (void)hipEventDestroy(s->pinned_done);
   if (s->pinned) (void)hipHostFree(s->pinned);
@@ -366,6 +388,10 @@ soax_status soax_buffer(const soax_set* set, int32_t index, void** ptr) {
     *ptr = set->aos;
     return SOAX_OK;
   }
+  if (index == -2) {
+    *ptr = set->aosoa;
+    return SOAX_OK;
+  }
   if (index < 0 || index >= set->L.narrays) return fail(SOAX_E_ARG, "array index %d out of range", index);
   *ptr = set->soa.empty() ? nullptr : set->soa[index];
   return SOAX_OK;
@@ -417,7 +443,7 @@ soax_status soax_fill(soax_set* set, uint64_t seed, int32_t vel_mode, const soax
 
 soax_status soax_step_config(soax_set* set, int32_t layout, int32_t block, int32_t per_thread) {
   if (!set) return fail(SOAX_E_ARG, "set is NULL");
-  if (layout < SOAX_SOA || layout > SOAX_AOS_NAIVE) return fail(SOAX_E_ARG, "unknown layout %d", layout);
+  if (layout < SOAX_SOA || layout > SOAX_AOSOA) return fail(SOAX_E_ARG, "unknown layout %d", layout);
   if (block != 0 && (block < 64 || block > 1024 || block % 64))
     return fail(SOAX_E_ARG, "block %d must be 0 or a multiple of 64 in 64..1024", block);
   if (per_thread != 0 && per_thread != 1 && per_thread != 2 && per_thread != 4)
@@ -432,7 +458,7 @@ soax_status soax_step_config(soax_set* set, int32_t layout, int32_t block, int32
 soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double dt, int64_t nsteps,
                       const soax_params* params, void* stream) {
   if (!set) return fail(SOAX_E_ARG, "set is NULL");
-  if (layout < SOAX_SOA || layout > SOAX_AOS_NAIVE) return fail(SOAX_E_ARG, "unknown layout %d", layout);
+  if (layout < SOAX_SOA || layout > SOAX_AOSOA) return fail(SOAX_E_ARG, "unknown layout %d", layout);
   if (integrator < SOAX_EULER || integrator > SOAX_SYMPLECTIC_EULER)
     return fail(SOAX_E_ARG, "unknown integrator %d", integrator);
   if (!is_finite(dt)) return fail(SOAX_E_ARG, "dt is not finite");
@@ -482,6 +508,27 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
               "SoA step launch");
     return SOAX_OK;
   }
+  if (layout == SOAX_AOSOA) {
+    if (!set->aosoa) return fail(SOAX_E_LAYOUT, "the set has no AoSoA copy");
+    std::vector<int32_t> off;
+    AosoaStepArgs a{};
+    a.base = set->aosoa;
+    a.tile_bytes = aosoa_tile(L, &off);
+    for (int d = 0; d < 3; ++d) {
+      a.off_pos[d] = off[L.f[fp].first_array + d];
+      a.off_vel[d] = off[L.f[fv].first_array + d];
+      a.off_acc[d] = fa >= 0 ? off[L.f[fa].first_array + d] : 0;
+    }
+    a.n = set->n;
+    a.dt = dt;
+    a.abc = abc;
+    a.wrap = wrap;
+    const int block = set->block[SOAX_AOSOA] ? set->block[SOAX_AOSOA] : 128;
+    for (int64_t k = 0; k < nsteps; ++k)
+      HIP_TRY(launch_aosoa_step(integrator, L.f[fp].dtype, L.f[fv].dtype, block, a, s),
+              "AoSoA step launch");
+    return SOAX_OK;
+  }
   if (!has_aos(set)) return fail(SOAX_E_LAYOUT, "the set has no AoS copy");
   AosStepArgs a{};
   a.aos = set->aos;
@@ -526,6 +573,74 @@ static soax_status xpose(soax_set* set, bool to_soa, void* stream) {
 soax_status soax_aos_to_soa(soax_set* set, void* stream) { return xpose(set, true, stream); }
 soax_status soax_soa_to_aos(soax_set* set, void* stream) { return xpose(set, false, stream); }
 
+soax_status soax_aosoa_layout(const soax_schema* schema, int64_t* array_offsets,
+                              int64_t* tile_bytes) {
+  Layout L;
+  soax_status st = parse_schema(schema, L);
+  if (st) return st;
+  std::vector<int32_t> off;
+  const int64_t tb = aosoa_tile(L, &off);
+  if (array_offsets)
+    for (int a = 0; a < L.narrays; ++a) array_offsets[a] = off[a];
+  if (tile_bytes) *tile_bytes = tb;
+  return SOAX_OK;
+}
+
+soax_status soax_bind_aosoa(soax_set* set, void* aosoa, int64_t bytes) {
+  if (!set) return fail(SOAX_E_ARG, "set is NULL");
+  if (!aosoa) {  // detach
+    set->aosoa = nullptr;
+    set->aosoa_bytes = 0;
+    return SOAX_OK;
+  }
+  const int64_t need = aosoa_need(set->L, set->cap);
+  if (bytes < need)
+    return fail(SOAX_E_ARG, "the AoSoA buffer holds %lld bytes; %lld are needed for %lld particles",
+                static_cast<long long>(bytes), static_cast<long long>(need),
+                static_cast<long long>(set->cap));
+  if (!aligned16(aosoa)) return fail(SOAX_E_LAYOUT, "the AoSoA buffer is not 16-byte aligned");
+  if (!has_soa(set)) return fail(SOAX_E_LAYOUT, "an AoSoA copy needs the SoA copy beside it");
+  std::vector<int32_t> off;
+  XposeArgs& t = set->aosoa_host;
+  t = XposeArgs{};
+  t.aos = static_cast<char*>(aosoa);
+  t.n = set->n;
+  t.stride = static_cast<int32_t>(aosoa_tile(set->L, &off));
+  t.narrays = set->L.narrays;
+  t.aligned = 1;
+  for (const Field& f : set->L.f)
+    for (int c = 0; c < f.dim; ++c) {
+      const int a = f.first_array + c;
+      t.soa[a] = static_cast<char*>(set->soa[a]);
+      t.off[a] = off[a];
+      t.es[a] = f.es;
+    }
+  if (!set->aosoa_dev) {
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(XposeArgs));
+    if (e != hipSuccess) return fail(SOAX_E_OOM, "hipMalloc(AoSoA table): %s", hipGetErrorString(e));
+    set->aosoa_dev = static_cast<XposeArgs*>(d);
+  }
+  HIP_TRY(hipMemcpy(set->aosoa_dev, &t, sizeof(XposeArgs), hipMemcpyHostToDevice),
+          "hipMemcpy(AoSoA table)");
+  set->aosoa = static_cast<char*>(aosoa);
+  set->aosoa_bytes = bytes;
+  return SOAX_OK;
+}
+
+static soax_status aosoa_xpose(soax_set* set, bool to_soa, void* stream) {
+  if (!set) return fail(SOAX_E_ARG, "set is NULL");
+  if (!set->aosoa) return fail(SOAX_E_LAYOUT, "the set has no AoSoA copy");
+  if (set->n == 0) return SOAX_OK;
+  XposeArgs h = set->aosoa_host;
+  h.n = set->n;
+  HIP_TRY(launch_aosoa_xpose(to_soa, h, set->aosoa_dev, as_stream(stream)), "AoSoA conversion launch");
+  return SOAX_OK;
+}
+
+soax_status soax_aosoa_to_soa(soax_set* set, void* stream) { return aosoa_xpose(set, true, stream); }
+soax_status soax_soa_to_aosoa(soax_set* set, void* stream) { return aosoa_xpose(set, false, stream); }
+
 soax_status soax_get_record(const soax_set* set, int32_t layout, int64_t i, void* host_record) {
   if (!set || !host_record) return fail(SOAX_E_ARG, "set or host_record is NULL");
   if (i < 0 || i >= set->n) return fail(SOAX_E_ARG, "record %lld out of range", static_cast<long long>(i));
@@ -536,7 +651,20 @@ soax_status soax_get_record(const soax_set* set, int32_t layout, int64_t i, void
     HIP_TRY(hipMemcpy(out, set->aos + i * L.stride, L.stride, hipMemcpyDeviceToHost), "hipMemcpy");
     return SOAX_OK;
   }
-  if (layout != SOAX_SOA) return fail(SOAX_E_ARG, "layout must be SOAX_SOA or SOAX_AOS");
+  if (layout == SOAX_AOSOA) {
+    if (!set->aosoa) return fail(SOAX_E_LAYOUT, "the set has no AoSoA copy");
+    std::vector<int32_t> off;
+    const int64_t tb = aosoa_tile(L, &off);
+    memset(out, 0, L.stride);
+    const char* tile = set->aosoa + (i / kAosoaW) * tb;
+    for (const Field& f : L.f)
+      for (int c = 0; c < f.dim; ++c)
+        HIP_TRY(hipMemcpy(out + f.off + c * f.es, tile + off[f.first_array + c] + (i % kAosoaW) * f.es,
+                          f.es, hipMemcpyDeviceToHost),
+                "hipMemcpy");
+    return SOAX_OK;
+  }
+  if (layout != SOAX_SOA) return fail(SOAX_E_ARG, "layout must be SOAX_SOA, SOAX_AOS or SOAX_AOSOA");
   if (set->soa.empty()) return fail(SOAX_E_LAYOUT, "the set has no SoA copy");
   memset(out, 0, L.stride);
   for (const Field& f : L.f)
@@ -582,6 +710,7 @@ soax_status grow(soax_set* set, int64_t cap, hipStream_t s) {
   set->soa = nsoa;
   set->aos = static_cast<char*>(naos);
   set->cap = cap;
+  set->aosoa = nullptr;  // the AoSoA table names the old SoA arrays
   ++set->generation;
   return finish_set(set);  // the stream is idle: the new table can be uploaded
 }
@@ -769,6 +898,7 @@ soax_status soax_rebind(soax_set* set, int64_t capacity, void* const* soa_ptrs, 
   if (soa_ptrs) set->soa.assign(soa_ptrs, soa_ptrs + set->L.narrays);
   set->aos = static_cast<char*>(aos_ptr);
   set->cap = capacity;
+  set->aosoa = nullptr;  // the AoSoA table names the old SoA arrays
   ++set->generation;
   return finish_set(set);
 }

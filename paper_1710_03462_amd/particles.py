@@ -70,7 +70,8 @@ class ParticleSet:
     them (to at least twice the capacity) through the library, which copies
     the particles into the new buffers."""
 
-    def __init__(self, fields, n, packed=False, soa=True, aos=True, pad=64, capacity=None):
+    def __init__(self, fields, n, packed=False, soa=True, aos=True, pad=64, capacity=None,
+                 aosoa=False):
         if not torch.cuda.is_available():
             raise RuntimeError("ParticleSet needs a GPU")
         self.schema = Schema(fields, packed)
@@ -85,9 +86,23 @@ class ParticleSet:
         check(lib().soax_bind_capacity(self.schema.ref, self.n, self.capacity, self._soa_ptrs(),
                                        self._aos_ptr(), ctypes.byref(h)), "soax_bind_capacity")
         self.handle = h
+        self._aosoa_store = None
+        if aosoa:
+            self._bind_aosoa()
         self._views()
 
     # --------------------------------------------------------------- storage
+    def _bind_aosoa(self):
+        """Allocate and attach a tiled (AoSoA) copy sized for the capacity."""
+        tile = ctypes.c_int64()
+        check(lib().soax_aosoa_layout(self.schema.ref, None, ctypes.byref(tile)),
+              "soax_aosoa_layout")
+        nbytes = max(-(-self.capacity // 64) * tile.value, 16)
+        self._aosoa_store = torch.zeros(nbytes, dtype=torch.uint8, device=self.device)
+        check(lib().soax_bind_aosoa(self.handle, ctypes.c_void_p(self._aosoa_store.data_ptr()),
+                                    nbytes), "soax_bind_aosoa")
+        self.aosoa_tile_bytes = tile.value
+
     def _alloc(self, cap):
         ld = max(self.pad, -(-cap // self.pad) * self.pad)
         self.capacity = min(ld, MAX_PARTICLES)  # the buffers' whole length, up to the limit
@@ -119,6 +134,8 @@ class ParticleSet:
         check(lib().soax_rebind(self.handle, self.capacity, self._soa_ptrs(), self._aos_ptr(),
                                 current_stream()), "soax_rebind")
         del old  # the library has copied the particles and synchronised
+        if self._aosoa_store is not None:  # the move detached it; attach a larger one
+            self._bind_aosoa()
 
     # -------------------------------------------------------------- lifetime
     def close(self):
@@ -219,6 +236,17 @@ class ParticleSet:
 
     def soa_to_aos(self):
         check(lib().soax_soa_to_aos(self.handle, current_stream()), "soax_soa_to_aos")
+
+    def soa_to_aosoa(self):
+        check(lib().soax_soa_to_aosoa(self.handle, current_stream()), "soax_soa_to_aosoa")
+
+    def aosoa_to_soa(self):
+        check(lib().soax_aosoa_to_soa(self.handle, current_stream()), "soax_aosoa_to_soa")
+
+    def download_aosoa(self):
+        """The tiled copy's bytes for the first ceil(n / 64) tiles."""
+        nt = -(-self.n // 64)
+        return self._aosoa_store[: nt * self.aosoa_tile_bytes].cpu().numpy()
 
     def get_record(self, layout, i):
         buf = (ctypes.c_uint8 * self.stride)()

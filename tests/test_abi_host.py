@@ -37,7 +37,8 @@ def test_header_declarations_match_binding_signatures():
              "soax_strerror", "soax_last_error", "soax_bind_capacity", "soax_capacity",
              "soax_reserve", "soax_resize", "soax_push_back", "soax_rebind", "soax_set_record",
              "soax_remove_flagged", "soax_eval", "soax_eval_ptrs", "soax_expr_source",
-             "soax_rk2_forward_ckpt_strided", "soax_adjoint_strided", "soax_sqdist_loss_strided"}
+             "soax_rk2_forward_ckpt_strided", "soax_adjoint_strided", "soax_sqdist_loss_strided",
+             "soax_aosoa_layout", "soax_bind_aosoa", "soax_soa_to_aosoa", "soax_aosoa_to_soa"}
     assert declared == bound
 
 
@@ -116,7 +117,11 @@ def test_step_validation(L, soa_only_set):
     p = _lib.Params(1.0, 1.0, 1.0, 1)
     bad = _lib.Params(math.nan, 1.0, 1.0, 1)
     s = ctypes.byref
-    assert L.soax_step(h, 3, 0, 1e-3, 1, s(p), None) == E_ARG          # unknown layout
+    assert L.soax_step(h, 4, 0, 1e-3, 1, s(p), None) == E_ARG          # unknown layout
+    assert L.soax_step(h, 3, 0, 1e-3, 1, s(p), None) == E_LAYOUT       # no AoSoA copy bound
+    assert L.soax_soa_to_aosoa(h, None) == E_LAYOUT
+    assert L.soax_bind_aosoa(h, ctypes.c_void_p(0x400000), 100) == E_ARG  # too small
+    assert L.soax_bind_aosoa(h, ctypes.c_void_p(0x400008), 1 << 20) == E_LAYOUT  # misaligned
     assert L.soax_step(h, 0, 7, 1e-3, 1, s(p), None) == E_ARG          # unknown integrator
     assert L.soax_step(h, 0, 0, math.inf, 1, s(p), None) == E_ARG      # dt
     assert L.soax_step(h, 0, 0, 1e-3, -1, s(p), None) == E_ARG         # nsteps
@@ -231,3 +236,14 @@ def test_bind_capacity_validation(L):
     assert L.soax_capacity(h, ctypes.byref(n), ctypes.byref(cap)) == 0
     assert (n.value, cap.value) == (10, 64)
     L.soax_destroy(h)
+
+
+def test_aosoa_layout_agrees_with_oracle(ref):
+    for fields in SCHEMAS:
+        sch, keep = _lib.make_schema(fields)
+        narr = sum(int(f[2]) for f in fields)
+        off = (ctypes.c_int64 * narr)()
+        tile = ctypes.c_int64()
+        assert _lib.lib().soax_aosoa_layout(ctypes.byref(sch), off, ctypes.byref(tile)) == 0
+        roff, rtile = ref.aosoa_layout(ref.Schema(fields))
+        assert (list(off), tile.value) == (roff, rtile)

@@ -105,6 +105,25 @@ def test_config1_integrator_variants_1e8(ref):
     ps.close()
 
 
+def test_config1_tiled_copy_1e8():
+    """The benchmark's AoSoA rows at the headline size: Euler and RK2 steps on
+    the tiled copy give the SoA kernels' results bit for bit (whole arrays)."""
+    n, abc = 100_000_000, [1.0, 1.0, 1.0]
+    ps = soax.ParticleSet(si.BASE_FIELDS, n, aos=False, aosoa=True)
+    ps.fill(seed=0, vel_mode=1, abc=abc)
+    ps.soa_to_aosoa()
+    for integ, steps in (("euler", 2), ("rk2_abc", 3)):
+        ps.step("aosoa", integ, 1e-3, steps, abc=abc, wrap=True)
+        ps.step("soa", integ, 1e-3, steps, abc=abc, wrap=True)
+    stepped = [t.clone() for t in ps.soa[1:]]
+    ps.aosoa_to_soa()
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(ps.soa[1:], stepped))
+    assert torch.equal(ps.soa[0], torch.arange(n, dtype=torch.int32, device="cuda"))
+    del stepped
+    ps.close()
+
+
 def test_config2_wide_transpose_and_steps_3e7(ref):
     n = 30_000_000
     fields = si.WIDE_FIELDS
