@@ -24,6 +24,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -42,11 +43,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_only(text):
+    """Source text without comments and blank space: a comment edit leaves the
+    compiled kernels, and so the counter data, valid."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "".join(text.split())
+
+
 def sources_hash():
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p) as f:
+            h.update(code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -12,10 +12,10 @@
  *  - the per-element copy between a record and the arrays (Section 1, the
  *    paragraph after Listing 3; Section 4.1, getElement/push_back), here in
  *    bulk form;
- *  - RK2 advection in the ABC field and its discrete adjoint, which the paper
- *    only names as a use ("temporary positions and velocities for a
- *    Runge-Kutta scheme", Section 2): their definitions are the explicit
- *    midpoint rule and its exact reverse-mode derivative, written out below.
+ *  - RK2 advection in the ABC field and its discrete adjoint; the paper only
+ *    mentions Runge-Kutta schemes as a reason records carry extra temporary
+ *    fields (Section 2), so their definitions are the explicit midpoint rule
+ *    and its exact reverse-mode derivative, written out below.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math (see build.py).
  */
