@@ -481,7 +481,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by particle range with no communication; see DESIGN.md)",
+              "(the path would shard by particle range with no communication; one GPU is measured)",
               file=sys.stderr)
         return 2
 
