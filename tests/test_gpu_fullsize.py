@@ -31,7 +31,7 @@ def gpu_slice(ps, r0, cnt):
     return [t[r0:r0 + cnt].cpu().numpy() for t in ps.soa]
 
 
-def test_config1_rk2_1e8(ref):
+def test_rk2_headline_1e8(ref):
     n, nsteps, abc = 100_000_000, 50, [1.0, 1.0, 1.0]
     fields = si.BASE_FIELDS
     sch = ref.Schema(fields)
@@ -73,7 +73,7 @@ def test_config1_rk2_1e8(ref):
     ps.close()
 
 
-def test_config1_integrator_variants_1e8(ref):
+def test_integrator_variants_1e8(ref):
     """Heun and RK4 on the headline set, as the benchmark's integrator row
     runs them (SoA, then the LDS-staged AoS copy), sampled against the oracle."""
     n, abc = 100_000_000, [1.0, 1.0, 1.0]
@@ -105,7 +105,7 @@ def test_config1_integrator_variants_1e8(ref):
     ps.close()
 
 
-def test_config1_tiled_copy_1e8():
+def test_tiled_copy_1e8():
     """The benchmark's AoSoA rows at the headline size: Euler and RK2 steps on
     the tiled copy give the SoA kernels' results bit for bit (whole arrays)."""
     n, abc = 100_000_000, [1.0, 1.0, 1.0]
@@ -124,7 +124,7 @@ def test_config1_tiled_copy_1e8():
     ps.close()
 
 
-def test_config2_wide_transpose_and_steps_3e7(ref):
+def test_wide_record_transposes_and_steps_3e7(ref):
     n = 30_000_000
     fields = si.WIDE_FIELDS
     sch = ref.Schema(fields)
@@ -183,7 +183,7 @@ def test_config2_wide_transpose_and_steps_3e7(ref):
                 assert_fields_close(got[a][~same], want[a][~same])
 
 
-def test_config3_adjoint_1e7(ref):
+def test_adjoint_1e7_200_steps(ref):
     n, nsteps, dt, k = 10_000_000, 200, 5e-3, 20
     abc = [1.0, 0.8, 0.6]
     x0, target = si.adjoint_inputs(n, seed=0)
@@ -219,7 +219,7 @@ def test_config3_adjoint_1e7(ref):
     assert torch.equal(gx2, gx) and torch.equal(gabc2, gabc) and torch.equal(xT2, xT)
 
 
-def test_config4_batch_256_sets(ref):
+def test_batch_256_uneven_sets(ref):
     sizes, dts, abc = si.batch_plan(256, seed=0)
     sets = []
     for s, n in enumerate(sizes):
