@@ -172,6 +172,28 @@ class ParticleSet:
                                    current_stream()), "soax_push_back")
         self._views()
 
+    def record_dtype(self):
+        """numpy structured dtype of one AoS record (the schema's C layout)."""
+        names, formats, offsets = [], [], []
+        for (name, t, d), off in zip(self.schema.fields, self.offsets):
+            names.append(name)
+            formats.append((NUMPY_DTYPE[t], (int(d),)) if int(d) > 1 else NUMPY_DTYPE[t])
+            offsets.append(off)
+        return np.dtype({"names": names, "formats": formats, "offsets": offsets,
+                         "itemsize": self.stride})
+
+    def element(self, i, layout="soa"):
+        """Particle i as a structured numpy record (a copy, like getElement)."""
+        return np.frombuffer(self.get_record(layout, i), dtype=self.record_dtype())[0].copy()
+
+    def set_element(self, i, rec=None, **fields):
+        """Write particle i in every copy from a record (as returned by
+        element()) and/or keyword field values, e.g. set_element(7, id=42)."""
+        r = np.array(self.element(i) if rec is None else rec, dtype=self.record_dtype())
+        for name, value in fields.items():
+            r[name] = value
+        self.set_record(i, r.tobytes())
+
     def set_record(self, i, record):
         buf = np.ascontiguousarray(np.frombuffer(bytes(record), np.uint8))
         if buf.size != self.stride:

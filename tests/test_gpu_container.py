@@ -235,3 +235,21 @@ def test_batch_refuses_a_resized_set():
         b.step(dts, abc, 1, mode=soax.PERSISTENT)
     assert e.value.status == -7
     b.close()
+
+
+def test_element_access_like_get_element():
+    fields = si.WIDE_FIELDS
+    ps, arrays = make_set(fields, False, 50, 8)
+    e = ps.element(7)
+    assert int(e["id"]) == int(arrays[ps.schema.array_index("id")][7])
+    assert float(e["pos"][1]) == float(arrays[ps.schema.array_index("pos", 1)][7])
+    ps.set_element(7, id=42, pos=[3.14, 1.0, 2.0])
+    e2 = ps.element(7, "aos")
+    assert int(e2["id"]) == 42 and list(e2["pos"]) == [3.14, 1.0, 2.0]
+    assert float(e2["mass"]) == float(arrays[ps.schema.array_index("mass")][7])
+    assert ps.get_record("soa", 7) == ps.get_record("aos", 7)
+    # push_back of a modified element, as in the paper's usage example
+    e2["id"] = 50
+    ps.push_back(e2.tobytes())
+    assert ps.n == 51 and int(ps.element(50)["id"]) == 50
+    ps.close()
