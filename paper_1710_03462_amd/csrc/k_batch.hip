@@ -19,66 +19,78 @@ namespace soax {
 
 namespace {
 
+// One tile of set S.  SMALL: small_steps holds for this set.
 template <typename VT, int PPT, bool SMALL>
-__global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
-  for (int64_t t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
-    const BatchSet& S = b.sets[b.tile_set[t]];
-    const Abc p{S.A, S.B, S.C};
-    const double dt = S.dt;
-    const int64_t i0 = (t - S.tile_begin) * b.tile + static_cast<int64_t>(threadIdx.x) * PPT;
-    double* px = S.pos[0];
-    double* py = S.pos[1];
-    double* pz = S.pos[2];
-    VT* vx = static_cast<VT*>(S.vel[0]);
-    VT* vy = static_cast<VT*>(S.vel[1]);
-    VT* vz = static_cast<VT*>(S.vel[2]);
-    if (i0 + PPT <= S.n) {
-      double x[PPT], y[PPT], z[PPT];
-      VT u[PPT], v[PPT], w[PPT];
-      ld_run<false, double, PPT>(px + i0, x);
-      ld_run<false, double, PPT>(py + i0, y);
-      ld_run<false, double, PPT>(pz + i0, z);
+__device__ __forceinline__ void batch_tile(const BatchSet& S, int64_t t, int32_t tile) {
+  const Abc p{S.A, S.B, S.C};
+  const double dt = S.dt;
+  const int64_t i0 = (t - S.tile_begin) * tile + static_cast<int64_t>(threadIdx.x) * PPT;
+  double* px = S.pos[0];
+  double* py = S.pos[1];
+  double* pz = S.pos[2];
+  VT* vx = static_cast<VT*>(S.vel[0]);
+  VT* vy = static_cast<VT*>(S.vel[1]);
+  VT* vz = static_cast<VT*>(S.vel[2]);
+  if (i0 + PPT <= S.n) {
+    double x[PPT], y[PPT], z[PPT];
+    VT u[PPT], v[PPT], w[PPT];
+    ld_run<false, double, PPT>(px + i0, x);
+    ld_run<false, double, PPT>(py + i0, y);
+    ld_run<false, double, PPT>(pz + i0, z);
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        u[j] = v[j] = w[j] = VT(0);
-        update_particle<kRk2Abc, double, VT, SMALL>(x[j], y[j], z[j], u[j], v[j], w[j], VT(0),
-                                                    VT(0), VT(0), dt, p, 1);
-      }
-      // the batch spans far more than the caches: nontemporal stores
-      st_run<true, double, PPT>(px + i0, x);
-      st_run<true, double, PPT>(py + i0, y);
-      st_run<true, double, PPT>(pz + i0, z);
-      st_run<true, VT, PPT>(vx + i0, u);
-      st_run<true, VT, PPT>(vy + i0, v);
-      st_run<true, VT, PPT>(vz + i0, w);
-    } else {
-      for (int64_t i = i0; i < S.n; ++i) {
-        double x = px[i], y = py[i], z = pz[i];
-        VT u = VT(0), v = VT(0), w = VT(0);
-        update_particle<kRk2Abc, double, VT, SMALL>(x, y, z, u, v, w, VT(0), VT(0), VT(0), dt, p,
-                                                    1);
-        px[i] = x;
-        py[i] = y;
-        pz[i] = z;
-        vx[i] = u;
-        vy[i] = v;
-        vz[i] = w;
-      }
+    for (int j = 0; j < PPT; ++j) {
+      u[j] = v[j] = w[j] = VT(0);
+      update_particle<kRk2Abc, double, VT, SMALL>(x[j], y[j], z[j], u[j], v[j], w[j], VT(0),
+                                                  VT(0), VT(0), dt, p, 1);
+    }
+    // the batch spans far more than the caches: nontemporal stores
+    st_run<true, double, PPT>(px + i0, x);
+    st_run<true, double, PPT>(py + i0, y);
+    st_run<true, double, PPT>(pz + i0, z);
+    st_run<true, VT, PPT>(vx + i0, u);
+    st_run<true, VT, PPT>(vy + i0, v);
+    st_run<true, VT, PPT>(vz + i0, w);
+  } else {
+    for (int64_t i = i0; i < S.n; ++i) {
+      double x = px[i], y = py[i], z = pz[i];
+      VT u = VT(0), v = VT(0), w = VT(0);
+      update_particle<kRk2Abc, double, VT, SMALL>(x, y, z, u, v, w, VT(0), VT(0), VT(0), dt, p,
+                                                  1);
+      px[i] = x;
+      py[i] = y;
+      pz[i] = z;
+      vx[i] = u;
+      vy[i] = v;
+      vz[i] = w;
     }
   }
 }
 
-template <typename VT, bool SMALL>
+// Every tile takes the unchecked angle-shift path when its own set's step
+// is provably small, the checked one otherwise (a branch uniform over the
+// workgroup, which works on one tile at a time).
+template <typename VT, int PPT>
+__global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
+  for (int64_t t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
+    const BatchSet& S = b.sets[b.tile_set[t]];
+    if (S.small)
+      batch_tile<VT, PPT, true>(S, t, b.tile);
+    else
+      batch_tile<VT, PPT, false>(S, t, b.tile);
+  }
+}
+
+template <typename VT>
 hipError_t batch_t(const BatchLaunch& b, hipStream_t s) {
   switch (b.per_thread) {
     case 1:
-      hipLaunchKernelGGL((batch_rk2_kernel<VT, 1, SMALL>), dim3(b.grid), dim3(b.block), 0, s, b);
+      hipLaunchKernelGGL((batch_rk2_kernel<VT, 1>), dim3(b.grid), dim3(b.block), 0, s, b);
       break;
     case 2:
-      hipLaunchKernelGGL((batch_rk2_kernel<VT, 2, SMALL>), dim3(b.grid), dim3(b.block), 0, s, b);
+      hipLaunchKernelGGL((batch_rk2_kernel<VT, 2>), dim3(b.grid), dim3(b.block), 0, s, b);
       break;
     default:
-      hipLaunchKernelGGL((batch_rk2_kernel<VT, 4, SMALL>), dim3(b.grid), dim3(b.block), 0, s, b);
+      hipLaunchKernelGGL((batch_rk2_kernel<VT, 4>), dim3(b.grid), dim3(b.block), 0, s, b);
       break;
   }
   return hipGetLastError();
@@ -88,8 +100,7 @@ hipError_t batch_t(const BatchLaunch& b, hipStream_t s) {
 
 hipError_t launch_batch_rk2(const BatchLaunch& b, hipStream_t s) {
   if (b.ntiles == 0) return hipSuccess;
-  if (b.small) return b.vel_t == kF64 ? batch_t<double, true>(b, s) : batch_t<float, true>(b, s);
-  return b.vel_t == kF64 ? batch_t<double, false>(b, s) : batch_t<float, false>(b, s);
+  return b.vel_t == kF64 ? batch_t<double>(b, s) : batch_t<float>(b, s);
 }
 
 }  // namespace soax

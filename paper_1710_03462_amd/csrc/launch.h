@@ -284,6 +284,8 @@ struct BatchSet {
   int64_t tile_begin;  // first tile of this set in the batch's tile list
   double dt;
   double A, B, C;
+  int32_t small;  // small_steps holds for this set's dt and amplitudes
+  int32_t reserved;
 };
 
 struct BatchLaunch {
@@ -296,7 +298,6 @@ struct BatchLaunch {
   int32_t per_thread;
   int32_t grid;
   int32_t vel_t;
-  int32_t small;  // small_steps holds for every set
 };
 hipError_t launch_batch_rk2(const BatchLaunch& b, hipStream_t s);
 

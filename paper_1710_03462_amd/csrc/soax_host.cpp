@@ -176,8 +176,7 @@ struct soax_batch {
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
   hipStream_t capture_stream = nullptr;
-  int small = 0;  // small_steps holds for every set's current dt and amplitudes
-  std::map<std::tuple<int64_t, int, int, int, int>, hipGraphExec_t> graphs;
+  std::map<std::tuple<int64_t, int, int, int>, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -1346,7 +1345,6 @@ BatchLaunch batch_launch(const soax_batch* b) {
   if (grid > b->ntiles) grid = b->ntiles;
   L.grid = static_cast<int32_t>(std::max<int64_t>(grid, 1));
   L.vel_t = b->vel_t;
-  L.small = b->small;
   return L;
 }
 
@@ -1356,9 +1354,8 @@ soax_status upload_params(soax_batch* b, const double* dt, const double* abc, hi
     HIP_TRY(hipEventSynchronize(b->stage_done), "hipEventSynchronize");
     b->stage_pending = false;
   }
-  int small = 1;
   for (size_t i = 0; i < b->sets.size(); ++i) {
-    if (!small_steps(dt[i], abc[3 * i], abc[3 * i + 1], abc[3 * i + 2])) small = 0;
+    b->stage[i].small = small_steps(dt[i], abc[3 * i], abc[3 * i + 1], abc[3 * i + 2]) ? 1 : 0;
     b->stage[i].dt = dt[i];
     b->stage[i].A = abc[3 * i];
     b->stage[i].B = abc[3 * i + 1];
@@ -1369,7 +1366,6 @@ soax_status upload_params(soax_batch* b, const double* dt, const double* abc, hi
           "hipMemcpyAsync(set table)");
   HIP_TRY(hipEventRecord(b->stage_done, s), "hipEventRecord");
   b->stage_pending = true;
-  b->small = small;
   return SOAX_OK;
 }
 
@@ -1402,7 +1398,7 @@ soax_status per_set_step(soax_batch* b, const double* dt, const double* abc, hip
 }
 
 soax_status graph_for(soax_batch* b, int64_t nsteps, hipGraphExec_t* out) {
-  auto key = std::make_tuple(nsteps, b->block, b->per_thread, b->blocks_per_cu, b->small);
+  auto key = std::make_tuple(nsteps, b->block, b->per_thread, b->blocks_per_cu);
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) {
     *out = it->second;
