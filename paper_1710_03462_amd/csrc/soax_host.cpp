@@ -1669,7 +1669,7 @@ extern "C" soax_status soax_batch_tune(soax_batch* b, const char* cache_path) {
   HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
   const int blocks[] = {128, 256, 512};
   const int ppts[] = {1, 2, 4};
-  const int bpcs[] = {2, 4, 8, 16};
+  const int bpcs[] = {2, 4, 8, 16, 32, 64};
   TuneEntry best{b->block, b->per_thread, b->blocks_per_cu, 1e30};
   for (int bl : blocks)
     for (int pp : ppts)
