@@ -4,6 +4,7 @@ oracle's, and invalid calls return their documented status before any
 device call is made."""
 import ctypes
 import math
+import os
 
 import pytest
 
@@ -13,6 +14,7 @@ soax = pytest.importorskip("paper_1710_03462_amd")
 from paper_1710_03462_amd import _lib  # noqa: E402
 
 E_ARG, E_SCHEMA, E_RANGE, E_LAYOUT = -1, -2, -3, -4
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module")
@@ -247,3 +249,32 @@ def test_aosoa_layout_agrees_with_oracle(ref):
         assert _lib.lib().soax_aosoa_layout(ctypes.byref(sch), off, ctypes.byref(tile)) == 0
         roff, rtile = ref.aosoa_layout(ref.Schema(fields))
         assert (list(off), tile.value) == (roff, rtile)
+
+
+def test_product_fails_loudly_without_the_library(tmp_path):
+    """With libsoax.so absent the package raises on first use: there is no
+    fallback implementation anywhere."""
+    import subprocess
+    import sys
+    code = ("import paper_1710_03462_amd._lib as L\n"
+            "L.LIB_PATH = '/nonexistent/libsoax.so'\n"
+            "L._lib = None\n"
+            "try:\n"
+            "    L.lib()\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', 'no CPU fallback' in str(e))\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       cwd=str(tmp_path), env={"PYTHONPATH": ROOT, "PATH": "/usr/bin:/bin"})
+    assert "raised: True" in r.stdout, r.stdout + r.stderr
+
+
+def test_product_never_imports_the_oracle():
+    import subprocess
+    import sys
+    code = ("import sys, paper_1710_03462_amd as s\n"
+            "s.lib(); s.Schema([('id', 'i32', 1), ('pos', 'f64', 3), ('vel', 'f32', 3)]).layout()\n"
+            "import bench\n"
+            "print('oracle' in sys.modules)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
+                       env={"PYTHONPATH": ROOT, "PATH": "/usr/bin:/bin"})
+    assert r.stdout.strip().endswith("False"), r.stdout + r.stderr
