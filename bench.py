@@ -153,7 +153,8 @@ def bench_euler(torch, soax, ps, n, nsteps, layout):
 
 def bench_small_euler(torch, soax, si, n=100_000, nsteps=100):
     """The 1e5-particle Euler workload: 4 MB of state, cache-resident and
-    launch-bound, reported as updates/s in every layout."""
+    launch-bound, reported as updates/s in every layout, with one launch per
+    step and with the steps replayed from a captured graph."""
     ps = soax.ParticleSet(si.BASE_FIELDS, n)
     ps.fill(seed=0)
     ps.soa_to_aos()
@@ -171,9 +172,18 @@ def bench_small_euler(torch, soax, si, n=100_000, nsteps=100):
         t1 = time.perf_counter()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        # the same steps captured once into a graph and replayed
+        g = ps.step_graph(lay, "euler", 1e-3, nsteps, wrap=True)
+        g.launch()
+        with Timer(torch) as tg:
+            for _ in range(5):
+                g.launch()
+        g.close()
         out[lay] = {"updates_per_s": rate(n * nsteps, t.ms), "us_per_step": t.ms * 1e3 / nsteps,
                     "call_us": (t1 - t0) * 1e6 / nsteps,
-                    "wall_us_per_step": (t2 - t0) * 1e6 / nsteps}
+                    "wall_us_per_step": (t2 - t0) * 1e6 / nsteps,
+                    "graph_us_per_step": tg.ms * 1e3 / (5 * nsteps),
+                    "graph_updates_per_s": rate(5 * n * nsteps, tg.ms)}
     ps.close()
     return out
 

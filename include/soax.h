@@ -188,6 +188,22 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
  */
 soax_status soax_step_config(soax_set* set, int32_t layout, int32_t block, int32_t per_thread);
 
+/*
+ * The nsteps launches of one soax_step call captured once into a hipGraph and
+ * replayed by soax_step_graph_launch with a single graph launch: the same
+ * results as soax_step with the same arguments, with less launch overhead for
+ * sets small enough to be launch-bound.  The buffers, n, dt and params are
+ * fixed at capture; a launch after the set changed size or buffers fails with
+ * STATE.  Create validates like soax_step (errors ARG, SCHEMA, LAYOUT) and
+ * synchronises nothing; the graph must be destroyed before the set.
+ */
+typedef struct soax_step_graph soax_step_graph;
+soax_status soax_step_graph_create(soax_set* set, int32_t layout, int32_t integrator, double dt,
+                                   int64_t nsteps, const soax_params* params,
+                                   soax_step_graph** out);
+soax_status soax_step_graph_launch(soax_step_graph* graph, void* stream);
+void soax_step_graph_destroy(soax_step_graph* graph);
+
 /* Bulk transposes between the two copies, byte-exact; soax_soa_to_aos
  * writes every padding byte of every record as 0.  Both need both copies. */
 soax_status soax_aos_to_soa(soax_set* set, void* stream);

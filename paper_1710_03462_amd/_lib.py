@@ -105,6 +105,9 @@ def lib():
         "soax_bind_aosoa": [vp, vp, i64],
         "soax_soa_to_aosoa": [vp, vp],
         "soax_aosoa_to_soa": [vp, vp],
+        "soax_step_graph_create": [vp, i32, i32, dbl, i64, pp, vp],
+        "soax_step_graph_launch": [vp, vp],
+        "soax_step_graph_destroy": [vp],
         "soax_copy": [vp, vp, i64, vp],
         "soax_strerror": [i32],
         "soax_last_error": [],
@@ -115,6 +118,7 @@ def lib():
         fn.restype = ctypes.c_int32
     L.soax_destroy.restype = None
     L.soax_batch_destroy.restype = None
+    L.soax_step_graph_destroy.restype = None
     L.soax_strerror.restype = ctypes.c_char_p
     L.soax_last_error.restype = ctypes.c_char_p
     _lib = L

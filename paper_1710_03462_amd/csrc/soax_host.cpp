@@ -179,6 +179,12 @@ struct soax_batch {
   std::map<std::tuple<int64_t, int, int, int>, hipGraphExec_t> graphs;
 };
 
+struct soax_step_graph {
+  soax_set* set = nullptr;
+  uint64_t generation = 0;  // of the set when captured
+  hipGraphExec_t exec = nullptr;
+};
+
 namespace {
 
 soax_status check_n(const Layout& L, int64_t n) {
@@ -571,6 +577,51 @@ static soax_status xpose(soax_set* set, bool to_soa, void* stream) {
 
 soax_status soax_aos_to_soa(soax_set* set, void* stream) { return xpose(set, true, stream); }
 soax_status soax_soa_to_aos(soax_set* set, void* stream) { return xpose(set, false, stream); }
+
+soax_status soax_step_graph_create(soax_set* set, int32_t layout, int32_t integrator, double dt,
+                                   int64_t nsteps, const soax_params* params,
+                                   soax_step_graph** out) {
+  if (!out) return fail(SOAX_E_ARG, "out is NULL");
+  *out = nullptr;
+  // every argument check of soax_step, with nothing launched
+  soax_status st = soax_step(set, layout, integrator, dt, 0, params, nullptr);
+  if (st) return st;
+  if (nsteps < 0) return fail(SOAX_E_ARG, "nsteps is negative");
+  hipStream_t cap = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = soax_step(set, layout, integrator, dt, nsteps, params, cap);
+    e = hipStreamEndCapture(cap, &g);
+  }
+  hipGraphExec_t ex = nullptr;
+  if (st == SOAX_OK && e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cap);
+  if (st) return st;
+  if (e != hipSuccess) return hip_fail(e, "step graph capture");
+  soax_step_graph* sg = new soax_step_graph();
+  sg->set = set;
+  sg->generation = set->generation;
+  sg->exec = ex;
+  *out = sg;
+  return SOAX_OK;
+}
+
+soax_status soax_step_graph_launch(soax_step_graph* g, void* stream) {
+  if (!g) return fail(SOAX_E_ARG, "graph is NULL");
+  if (g->set->generation != g->generation)
+    return fail(SOAX_E_STATE, "the set changed size or buffers since the steps were captured");
+  HIP_TRY(hipGraphLaunch(g->exec, as_stream(stream)), "hipGraphLaunch");
+  return SOAX_OK;
+}
+
+void soax_step_graph_destroy(soax_step_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  delete g;
+}
 
 soax_status soax_aosoa_layout(const soax_schema* schema, int64_t* array_offsets,
                               int64_t* tile_bytes) {

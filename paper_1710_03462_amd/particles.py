@@ -249,6 +249,10 @@ class ParticleSet:
         check(lib().soax_step(self.handle, lay, integ, float(dt), int(nsteps), ctypes.byref(p),
                               current_stream()), "soax_step")
 
+    def step_graph(self, layout, integrator, dt, nsteps, abc=None, wrap=True):
+        """The nsteps launches of step() captured once; call .launch() to replay."""
+        return StepGraph(self, layout, integrator, dt, nsteps, abc, wrap)
+
     def step_config(self, layout, block=0, per_thread=0):
         lay = _lib.LAYOUTS[layout] if isinstance(layout, str) else layout
         check(lib().soax_step_config(self.handle, lay, block, per_thread), "soax_step_config")
@@ -293,6 +297,35 @@ class ParticleSet:
 
     def download_aos(self):
         return self.aos[: self.n * self.stride].cpu().numpy()
+
+
+class StepGraph:
+    """A captured sequence of steps of one set (soax_step_graph_*)."""
+
+    def __init__(self, ps, layout, integrator, dt, nsteps, abc=None, wrap=True):
+        lay = _lib.LAYOUTS[layout] if isinstance(layout, str) else layout
+        integ = _lib.INTEGRATORS[integrator] if isinstance(integrator, str) else integrator
+        p = params(abc, wrap)
+        h = ctypes.c_void_p()
+        check(lib().soax_step_graph_create(ps.handle, lay, integ, float(dt), int(nsteps),
+                                           ctypes.byref(p), ctypes.byref(h)),
+              "soax_step_graph_create")
+        self.set = ps  # keeps the set alive while the graph exists
+        self.handle = h
+
+    def launch(self):
+        check(lib().soax_step_graph_launch(self.handle, current_stream()), "soax_step_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().soax_step_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def copy(dst, src):

@@ -40,7 +40,8 @@ def test_header_declarations_match_binding_signatures():
              "soax_reserve", "soax_resize", "soax_push_back", "soax_rebind", "soax_set_record",
              "soax_remove_flagged", "soax_eval", "soax_eval_ptrs", "soax_expr_source",
              "soax_rk2_forward_ckpt_strided", "soax_adjoint_strided", "soax_sqdist_loss_strided",
-             "soax_aosoa_layout", "soax_bind_aosoa", "soax_soa_to_aosoa", "soax_aosoa_to_soa"}
+             "soax_aosoa_layout", "soax_bind_aosoa", "soax_soa_to_aosoa", "soax_aosoa_to_soa",
+             "soax_step_graph_create", "soax_step_graph_launch", "soax_step_graph_destroy"}
     assert declared == bound
 
 

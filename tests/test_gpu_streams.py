@@ -80,3 +80,38 @@ def test_steps_captured_in_a_graph(ref, layout):
         ref.step_soa(sch, want, ref.EULER, 1e-3, 1, wrap=True)
         torch.cuda.synchronize()
     ps.close()
+
+
+@pytest.mark.parametrize("layout", ["soa", "aos", "aosoa"])
+def test_step_graph_matches_eager_steps(ref, layout):
+    """soax_step_graph: the captured steps replayed several times, with eager
+    steps between, equal the oracle's; a resized set refuses the graph."""
+    fields = si.WIDE_FIELDS
+    sch = ref.Schema(fields)
+    n = 10_007
+    arrays = si.random_state(fields, n, 12)
+    ps = soax.ParticleSet(fields, n, aosoa=True)
+    ps.upload_soa(arrays)
+    ps.soa_to_aos()
+    ps.soa_to_aosoa()
+    g = ps.step_graph(layout, "euler_acc", 1e-3, 4, wrap=True)
+    want = [a.copy() for a in arrays]
+    for rep in range(3):
+        g.launch()
+        ref.step_soa(sch, want, ref.EULER_ACC, 1e-3, 4, wrap=True)
+        ps.step(layout, "euler_acc", 1e-3, 1, wrap=True)
+        ref.step_soa(sch, want, ref.EULER_ACC, 1e-3, 1, wrap=True)
+        torch.cuda.synchronize()
+    if layout == "aos":
+        ps.aos_to_soa()
+    elif layout == "aosoa":
+        ps.aosoa_to_soa()
+    torch.cuda.synchronize()
+    got = ps.download_soa()
+    assert all(np.array_equal(a.view(np.uint8), b.view(np.uint8)) for a, b in zip(got, want))
+    ps.resize(n - 7)
+    with pytest.raises(soax.SoaxError) as e:
+        g.launch()
+    assert e.value.status == -7
+    g.close()
+    ps.close()
