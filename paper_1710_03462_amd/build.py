@@ -15,8 +15,9 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsoax.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["soax_host.cpp", "expr.cpp", "k_step.hip", "k_adjoint.hip", "k_batch.hip",
-           "k_container.hip"]
+SOURCES = ["soax_host.cpp", "host_common.cpp", "host_containers.cpp", "host_expr.cpp",
+           "host_adjoint.cpp", "host_batch.cpp", "expr.cpp", "k_step.hip", "k_adjoint.hip",
+           "k_batch.hip", "k_container.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
