@@ -189,7 +189,10 @@ class ParticleSet:
     def set_element(self, i, rec=None, **fields):
         """Write particle i in every copy from a record (as returned by
         element()) and/or keyword field values, e.g. set_element(7, id=42)."""
-        r = np.array(self.element(i) if rec is None else rec, dtype=self.record_dtype())
+        raw = self.get_record("soa" if self._has_soa else "aos", i) if rec is None \
+            else np.asarray(rec).tobytes()
+        # work on the record's own bytes so that padding keeps its value
+        r = np.frombuffer(bytearray(raw), dtype=self.record_dtype())
         for name, value in fields.items():
             r[name] = value
         self.set_record(i, r.tobytes())
