@@ -84,9 +84,13 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
     PT x[VEC], y[VEC], z[VEC];
     VT u[VEC], v[VEC], w[VEC];
     VT ga[VEC], gb[VEC], gc[VEC];
+    // field steps: a wave issuing its loads or stores goes ahead of waves in
+    // their arithmetic, so memory requests leave early (measured ~1% faster)
+    if constexpr (field_integrator(INTEG)) __builtin_amdgcn_s_setprio(3);
     ld_run<false, PT, VEC>(px + i0, x);
     ld_run<false, PT, VEC>(py + i0, y);
     ld_run<false, PT, VEC>(pz + i0, z);
+    if constexpr (field_integrator(INTEG)) __builtin_amdgcn_s_setprio(0);
     if constexpr (kReadsVel) {
       ld_run<kNtVelLoad, VT, VEC>(vx + i0, u);
       ld_run<kNtVelLoad, VT, VEC>(vy + i0, v);
@@ -106,6 +110,7 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
       update_particle<INTEG, PT, VT, SMALL>(x[j], y[j], z[j], u[j], v[j], w[j], ga[j], gb[j],
                                             gc[j], a.dt, p, a.wrap);
     }
+    if constexpr (field_integrator(INTEG)) __builtin_amdgcn_s_setprio(3);
     st_run<STREAM, PT, VEC>(px + i0, x);
     st_run<STREAM, PT, VEC>(py + i0, y);
     st_run<STREAM, PT, VEC>(pz + i0, z);
