@@ -442,7 +442,8 @@ soax_status soax_batch_get_config(const soax_batch* batch, int32_t* block, int32
 /*
  * Autotune the persistent kernel's shape by timing candidate shapes on the
  * batch itself (state saved and restored, so particles do not move) and keep
- * the fastest.  If cache_path is not NULL the choice is looked up in / added
+ * the fastest.  Candidates: block 128/256/512, particles per thread 1/2/4,
+ * workgroups per CU 2/4/8/16/32/64.  If cache_path is not NULL the choice is looked up in / added
  * to that JSON file, keyed by device architecture, set count and particle
  * count.  Synchronises the device.
  */
