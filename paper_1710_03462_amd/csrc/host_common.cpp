@@ -128,6 +128,7 @@ soax_status finish_set(soax_set* s) {
       t.es[a] = f.es;
     }
   }
+  group_by_size(t);
   if (s->cap > 0 && has_soa(s) && has_aos(s)) {
     if (!s->xpose_dev) {
       void* d = nullptr;

@@ -193,6 +193,7 @@ soax_status soax_push_back(soax_set* set, const void* host_records, int64_t coun
           t.es[a] = f.es;
         }
       }
+      group_by_size(t);
       HIP_TRY(table.alloc(sizeof(XposeArgs), s), "hipMallocAsync(table)");
       HIP_TRY(hipMemcpyAsync(table.p, &t, sizeof(XposeArgs), hipMemcpyHostToDevice, s),
               "hipMemcpyAsync(table)");

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "device_math.h"
 #include "launch.h"
 
@@ -248,12 +250,26 @@ __device__ __forceinline__ void update_record(char* rec, const AosStepArgs& a, c
 // NT: nontemporal global accesses (see ld_run).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Each thread issues up to kStageLoads chunk loads before it writes any of
+// them to LDS, so a wave keeps several requests in flight instead of waiting
+// on one chunk at a time.
+constexpr int kStageLoads = 4;
+
 template <bool NT>
 __device__ __forceinline__ void stage_in(char* lds, const char* g, int nbytes) {
   const int nchunk = nbytes >> 4;
   const u32x4* src = reinterpret_cast<const u32x4*>(g);
   u32x4* dst = reinterpret_cast<u32x4*>(lds);
-  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) dst[c] = ld1<NT>(src + c);
+  const int step = static_cast<int>(blockDim.x);
+  for (int c0 = threadIdx.x; c0 < nchunk; c0 += kStageLoads * step) {
+    u32x4 v[kStageLoads];
+#pragma unroll
+    for (int j = 0; j < kStageLoads; ++j)
+      if (c0 + j * step < nchunk) v[j] = ld1<NT>(src + c0 + j * step);
+#pragma unroll
+    for (int j = 0; j < kStageLoads; ++j)
+      if (c0 + j * step < nchunk) dst[c0 + j * step] = v[j];
+  }
   for (int b = (nchunk << 4) + threadIdx.x; b < nbytes; b += blockDim.x) lds[b] = g[b];
 }
 
@@ -348,25 +364,51 @@ hipError_t aos_dispatch(int pos_t, int vel_t, bool aligned, bool naive, int bloc
 
 // ------------------------------------------------------------- transposes
 
-// Copy `es` bytes (1, 4 or 8).
-template <bool ALIGNED>
-__device__ __forceinline__ void copy_elem(char* dst, const char* src, int es) {
-  if constexpr (ALIGNED) {
-    if (es == 8)
-      *reinterpret_cast<uint64_t*>(dst) = *reinterpret_cast<const uint64_t*>(src);
-    else if (es == 4)
-      *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(src);
-    else
-      *dst = *src;
-  } else {
-    for (int b = 0; b < es; ++b) dst[b] = src[b];
+// Arrays whose elements one thread loads before it stores any of them, so
+// that a wave has several independent loads in flight.  The arrays come in
+// groups of one element size (XposeArgs::order); each group is walked in
+// blocks of kXposeGroup arrays and one final block of the remainder, every
+// block straight-line code: all its loads, then all its stores.
+constexpr int kXposeGroup = 4;
+
+template <typename F>
+__device__ __forceinline__ void for_blocks(int b, int e, F&& f) {
+  int a0 = b;
+  for (; a0 + kXposeGroup <= e; a0 += kXposeGroup) f(std::integral_constant<int, kXposeGroup>{}, a0);
+  switch (e - a0) {
+    case 3: f(std::integral_constant<int, 3>{}, a0); break;
+    case 2: f(std::integral_constant<int, 2>{}, a0); break;
+    case 1: f(std::integral_constant<int, 1>{}, a0); break;
+    default: break;
   }
 }
 
-// Element of width es at `src` (es = 1, 4 or 8) copied to `dst`.
-template <bool ALIGNED>
-__device__ __forceinline__ void copy_es(char* dst, const char* src, int es) {
-  copy_elem<ALIGNED>(dst, src, es);
+// Element i of arrays order[b..e) (element type T) into the record `rec`.
+template <typename T, bool ALIGNED, bool NT>
+__device__ __forceinline__ void gather_size(const XposeArgs& t, int b, int e, int64_t i,
+                                            char* rec) {
+  for_blocks(b, e, [&](auto G, int a0) {
+    T v[G.value];
+#pragma unroll
+    for (int j = 0; j < G.value; ++j)
+      v[j] = ld1<NT>(reinterpret_cast<const T*>(t.soa[t.order[a0 + j]]) + i);
+#pragma unroll
+    for (int j = 0; j < G.value; ++j) rec_store<T, ALIGNED>(rec + t.off[t.order[a0 + j]], v[j]);
+  });
+}
+
+// The record `rec`'s fields of arrays order[b..e) into element i of each.
+template <typename T, bool ALIGNED, bool NT>
+__device__ __forceinline__ void scatter_size(const XposeArgs& t, int b, int e, int64_t i,
+                                             const char* rec) {
+  for_blocks(b, e, [&](auto G, int a0) {
+    T v[G.value];
+#pragma unroll
+    for (int j = 0; j < G.value; ++j) v[j] = rec_load<T, ALIGNED>(rec + t.off[t.order[a0 + j]]);
+#pragma unroll
+    for (int j = 0; j < G.value; ++j)
+      st1<NT>(reinterpret_cast<T*>(t.soa[t.order[a0 + j]]) + i, v[j]);
+  });
 }
 
 // AoS -> SoA: the tile's records are staged through LDS with coalesced 16-byte
@@ -384,23 +426,11 @@ __global__ __launch_bounds__(256) void aos_to_soa_kernel(const XposeArgs* __rest
   const int stride = t.stride;
   stage_in<STREAM>(lds, t.aos + r0 * stride, nrec * stride);
   __syncthreads();
-  const int na = t.narrays;
-  for (int a = 0; a < na; ++a) {
-    const int es = t.es[a];
-    const int off = t.off[a];
-    char* dst = t.soa[a] + r0 * es;
-    if (ALIGNED && STREAM && es == 8) {
-      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
-        st1<true>(reinterpret_cast<uint64_t*>(dst) + r,
-                  *reinterpret_cast<const uint64_t*>(lds + r * stride + off));
-    } else if (ALIGNED && STREAM && es == 4) {
-      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
-        st1<true>(reinterpret_cast<uint32_t*>(dst) + r,
-                  *reinterpret_cast<const uint32_t*>(lds + r * stride + off));
-    } else {
-      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
-        copy_es<ALIGNED>(dst + r * es, lds + r * stride + off, es);
-    }
+  for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
+    const char* rec = lds + r * stride;
+    scatter_size<uint64_t, ALIGNED, STREAM>(t, 0, t.group_end[0], r0 + r, rec);
+    scatter_size<uint32_t, ALIGNED, STREAM>(t, t.group_end[0], t.group_end[1], r0 + r, rec);
+    scatter_size<uint8_t, ALIGNED, false>(t, t.group_end[1], t.group_end[2], r0 + r, rec);
   }
 }
 
@@ -420,23 +450,11 @@ __global__ __launch_bounds__(256) void soa_to_aos_kernel(const XposeArgs* __rest
   for (int c = threadIdx.x; c < (nbytes + 15) >> 4; c += blockDim.x)
     lds_u4[c] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
-  const int na = t.narrays;
-  for (int a = 0; a < na; ++a) {
-    const int es = t.es[a];
-    const int off = t.off[a];
-    const char* src = t.soa[a] + r0 * es;
-    if (ALIGNED && STREAM && es == 8) {
-      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
-        *reinterpret_cast<uint64_t*>(lds + r * stride + off) =
-            ld1<true>(reinterpret_cast<const uint64_t*>(src) + r);
-    } else if (ALIGNED && STREAM && es == 4) {
-      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
-        *reinterpret_cast<uint32_t*>(lds + r * stride + off) =
-            ld1<true>(reinterpret_cast<const uint32_t*>(src) + r);
-    } else {
-      for (int r = threadIdx.x; r < nrec; r += blockDim.x)
-        copy_es<ALIGNED>(lds + r * stride + off, src + r * es, es);
-    }
+  for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
+    char* rec = lds + r * stride;
+    gather_size<uint64_t, ALIGNED, STREAM>(t, 0, t.group_end[0], r0 + r, rec);
+    gather_size<uint32_t, ALIGNED, STREAM>(t, t.group_end[0], t.group_end[1], r0 + r, rec);
+    gather_size<uint8_t, ALIGNED, false>(t, t.group_end[1], t.group_end[2], r0 + r, rec);
   }
   __syncthreads();
   stage_out<STREAM>(t.aos + r0 * stride, lds, nbytes);
@@ -450,6 +468,39 @@ __device__ __forceinline__ T* tile_elem(char* base, int64_t tile_bytes, int32_t 
   return reinterpret_cast<T*>(base + (i / kAosoaW) * tile_bytes + off) + (i % kAosoaW);
 }
 
+// SoA <-> AoSoA for arrays order[b..e) (element type T): lane `lane` of
+// `tile` is particle i.  Lanes past n (the last tile's padding) are written
+// as zero bytes on the tile side and never stored on the SoA side; they load
+// element n - 1 (n >= 1) so that no load needs a branch.
+template <typename T, bool TO_SOA>
+__device__ __forceinline__ void aosoa_size(const XposeArgs& t, int b, int e, char* tile, int lane,
+                                           int64_t i, int64_t n) {
+  const bool live = i < n;
+  const int64_t ic = live ? i : n - 1;
+  for_blocks(b, e, [&](auto G, int a0) {
+    T v[G.value];
+#pragma unroll
+    for (int j = 0; j < G.value; ++j) {
+      const int a = t.order[a0 + j];
+      if constexpr (TO_SOA) {
+        v[j] = reinterpret_cast<const T*>(tile + t.off[a])[lane];
+      } else {
+        const T x = reinterpret_cast<const T*>(t.soa[a])[ic];
+        v[j] = live ? x : T(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < G.value; ++j) {
+      const int a = t.order[a0 + j];
+      if constexpr (TO_SOA) {
+        if (live) reinterpret_cast<T*>(t.soa[a])[i] = v[j];
+      } else {
+        reinterpret_cast<T*>(tile + t.off[a])[lane] = v[j];
+      }
+    }
+  });
+}
+
 // SoA <-> AoSoA: one thread per particle lane; the 64 lanes of a wave cover
 // one tile, so both sides of every copy are contiguous runs.
 template <bool TO_SOA>
@@ -461,17 +512,9 @@ __global__ __launch_bounds__(256) void aosoa_xpose_kernel(const XposeArgs* __res
   if (i >= lanes) return;
   char* tile = t.aos + (i / kAosoaW) * t.stride;
   const int lane = static_cast<int>(i % kAosoaW);
-  const int na = t.narrays;
-  for (int a = 0; a < na; ++a) {
-    const int es = t.es[a];
-    char* e = tile + t.off[a] + lane * es;
-    if (i < n) {
-      if constexpr (TO_SOA) copy_elem<true>(t.soa[a] + i * es, e, es);
-      else copy_elem<true>(e, t.soa[a] + i * es, es);
-    } else if constexpr (!TO_SOA) {
-      for (int b = 0; b < es; ++b) e[b] = 0;
-    }
-  }
+  aosoa_size<uint64_t, TO_SOA>(t, 0, t.group_end[0], tile, lane, i, n);
+  aosoa_size<uint32_t, TO_SOA>(t, t.group_end[0], t.group_end[1], tile, lane, i, n);
+  aosoa_size<uint8_t, TO_SOA>(t, t.group_end[1], t.group_end[2], tile, lane, i, n);
 }
 
 template <int INTEG, typename PT, typename VT, bool SMALL, bool STREAM>

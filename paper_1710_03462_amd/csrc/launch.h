@@ -101,7 +101,20 @@ struct XposeArgs {
   char* soa[kMaxArrays];
   int32_t off[kMaxArrays];  // byte offset of the element inside the record
   int32_t es[kMaxArrays];   // element size
+  int32_t order[kMaxArrays];  // array indices grouped by size: 8-byte, 4-byte, then 1-byte
+  int32_t group_end[3];       // end of each size's group in order[]
 };
+
+// Fill order and group_end from es[0..narrays) (element sizes 8, 4 or 1).
+inline void group_by_size(XposeArgs& t) {
+  const int32_t sizes[3] = {8, 4, 1};
+  int k = 0;
+  for (int g = 0; g < 3; ++g) {
+    for (int a = 0; a < t.narrays; ++a)
+      if (t.es[a] == sizes[g]) t.order[k++] = a;
+    t.group_end[g] = k;
+  }
+}
 
 // `host` is a host copy of the table the kernels read from `dev` (device
 // memory, uploaded when the set's buffers change); host.n is passed by value.

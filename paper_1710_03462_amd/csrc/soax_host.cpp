@@ -386,6 +386,7 @@ soax_status soax_bind_aosoa(soax_set* set, void* aosoa, int64_t bytes) {
       t.off[a] = off[a];
       t.es[a] = f.es;
     }
+  group_by_size(t);
   if (!set->aosoa_dev) {
     void* d = nullptr;
     hipError_t e = hipMalloc(&d, sizeof(XposeArgs));
