@@ -377,6 +377,7 @@ def bench_batch(torch, soax, si, nsets=256, nsteps=100):
         sets.append(ps)
     total = int(sizes.sum())
     b = soax.Batch(sets)
+    b.step(dts, abc, 1, mode=soax.PERSISTENT)  # the tuner times the last step's dt and amplitudes
     t0 = time.perf_counter()
     cfg = b.tune()
     tune_s = time.perf_counter() - t0

@@ -431,19 +431,25 @@ void soax_batch_destroy(soax_batch* batch);
 soax_status soax_batch_step(soax_batch* batch, const double* dt, const double* abc, int64_t nsteps,
                             int32_t mode, void* stream);
 
-/* Set the persistent kernel's shape: block threads (64..512, multiple of 64),
- * particles per thread (1, 2 or 4) and workgroups per CU (1..64); 0 keeps the
- * current value. */
+/* Set the batch kernel's shape: block threads (64..512, multiple of 64),
+ * particles per thread (1, 2 or 4) and workgroups per CU (1..65536); 0 keeps
+ * the current value.  The grid is min(CUs x blocks_per_cu, tiles) workgroups
+ * walking the tile list with a grid stride, so a value of at least
+ * tiles / CUs gives every tile its own workgroup (the default, with block 256
+ * and 1 particle per thread). */
 soax_status soax_batch_config(soax_batch* batch, int32_t block, int32_t per_thread,
                               int32_t blocks_per_cu);
 soax_status soax_batch_get_config(const soax_batch* batch, int32_t* block, int32_t* per_thread,
                                   int32_t* blocks_per_cu);
 
 /*
- * Autotune the persistent kernel's shape by timing candidate shapes on the
+ * Autotune the batch kernel's shape by timing candidate shapes on the
  * batch itself (state saved and restored, so particles do not move) and keep
  * the fastest.  Candidates: block 128/256/512, particles per thread 1/2/4,
- * workgroups per CU 2/4/8/16/32/64.  If cache_path is not NULL the choice is looked up in / added
+ * workgroups per CU 2/4/8/16/32/64 and 65536 (one tile per workgroup); the
+ * four fastest and the shape in use are timed again with longer runs before
+ * the choice.  The runs use the dt and amplitudes of the most recent
+ * soax_batch_step (dt = 1e-3, A = B = C = 1 before the first).  If cache_path is not NULL the choice is looked up in / added
  * to that JSON file, keyed by device architecture, set count and particle
  * count.  Synchronises the device.
  */

@@ -47,6 +47,9 @@ class Batch:
         return tuple(x.value for x in v)
 
     def tune(self, cache_path=None):
+        """Time candidate kernel shapes on this batch (its particles are left
+        as they were) with the dt and amplitudes of the most recent step(),
+        keep the fastest and return it as (block, per_thread, blocks_per_cu)."""
         check(lib().soax_batch_tune(self.handle, cache_path.encode() if cache_path else None),
               "soax_batch_tune")
         return self.get_config()

@@ -17,12 +17,18 @@
 using namespace soax;
 using namespace soax::host;
 
+// Upper bound of blocks_per_cu: with 256 CUs the grid can then cover
+// 16.7M tiles, more than the particle limit needs at 128-particle tiles.
+constexpr int kMaxBlocksPerCu = 65536;
+
 struct soax_batch {
   std::vector<soax_set*> sets;
   std::vector<uint64_t> generations;  // of each set when the batch was made
   int vel_t = kF32;
   int64_t total = 0;
-  int block = 256, per_thread = 2, blocks_per_cu = 8;
+  // default: one tile per workgroup (the grid covers every tile), one
+  // particle per thread -- the fastest shape on the uneven 256-set batch
+  int block = 256, per_thread = 1, blocks_per_cu = kMaxBlocksPerCu;
   int cus = 256;
   std::string arch;
   // device tables
@@ -36,6 +42,9 @@ struct soax_batch {
   bool stage_pending = false;
   hipStream_t capture_stream = nullptr;
   std::map<std::tuple<int64_t, int, int, int>, hipGraphExec_t> graphs;
+  // dt and amplitudes of the most recent step (empty before the first); the
+  // tuner times its candidates with them
+  std::vector<double> last_dt, last_abc;
 };
 
 // --------------------------------------------------------------- batching
@@ -260,7 +269,8 @@ soax_status soax_batch_config(soax_batch* b, int32_t block, int32_t per_thread, 
     return fail(SOAX_E_ARG, "block %d must be 0 or a multiple of 64 in 64..512", block);
   if (per_thread != 0 && per_thread != 1 && per_thread != 2 && per_thread != 4)
     return fail(SOAX_E_ARG, "per_thread %d must be 0, 1, 2 or 4", per_thread);
-  if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(SOAX_E_ARG, "blocks_per_cu must be 0..64");
+  if (blocks_per_cu < 0 || blocks_per_cu > kMaxBlocksPerCu)
+    return fail(SOAX_E_ARG, "blocks_per_cu must be 0..%d", kMaxBlocksPerCu);
   if (block) b->block = block;
   if (per_thread) b->per_thread = per_thread;
   if (blocks_per_cu) b->blocks_per_cu = blocks_per_cu;
@@ -290,6 +300,8 @@ soax_status soax_batch_step(soax_batch* b, const double* dt, const double* abc, 
     for (int j = 0; j < 3; ++j)
       if (!is_finite(abc[3 * i + j])) return fail(SOAX_E_ARG, "abc[%zu] is not finite", 3 * i + j);
   }
+  b->last_dt.assign(dt, dt + b->sets.size());
+  b->last_abc.assign(abc, abc + 3 * b->sets.size());
   hipStream_t s = as_stream(stream);
   if (nsteps == 0) return SOAX_OK;
   if (mode == 0) {
@@ -411,34 +423,66 @@ extern "C" soax_status soax_batch_tune(soax_batch* b, const char* cache_path) {
   Snapshot snap;
   soax_status st = snapshot(b, snap, false);
   if (st) return st;
-  // timing runs use the amplitudes and dt already in the device table
-  std::vector<double> dts(b->sets.size(), 1e-3), abc(3 * b->sets.size(), 1.0);
+  // candidates are timed with the most recent step's dt and amplitudes, or
+  // dt = 1e-3 and A = B = C = 1 before the first step
+  std::vector<double> dts = b->last_dt, abc = b->last_abc;
+  if (dts.empty()) {
+    dts.assign(b->sets.size(), 1e-3);
+    abc.assign(3 * b->sets.size(), 1.0);
+  }
   if ((st = upload_params(b, dts.data(), abc.data(), nullptr))) return st;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
   HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+  // average time of `reps` launches in one shape, after one warm-up launch
+  auto time_shape = [&](const TuneEntry& c, int reps, double* ms_out) -> soax_status {
+    soax_status cs = soax_batch_config(b, c.block, c.per_thread, c.blocks_per_cu);
+    if (cs) return cs;
+    const BatchLaunch L = batch_launch(b);
+    hipError_t e = launch_batch_rk2(L, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_batch_rk2(L, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) return hip_fail(e, "tuning run");
+    *ms_out = ms / reps;
+    return SOAX_OK;
+  };
   const int blocks[] = {128, 256, 512};
   const int ppts[] = {1, 2, 4};
-  const int bpcs[] = {2, 4, 8, 16, 32, 64};
-  TuneEntry best{b->block, b->per_thread, b->blocks_per_cu, 1e30};
+  // the last candidate gives every tile its own workgroup
+  const int bpcs[] = {2, 4, 8, 16, 32, 64, kMaxBlocksPerCu};
+  const TuneEntry current{b->block, b->per_thread, b->blocks_per_cu, 0.0};
+  // pass 1: every shape, 3 launches each
+  std::vector<TuneEntry> timed;
   for (int bl : blocks)
     for (int pp : ppts)
       for (int bc : bpcs) {
-        if ((st = soax_batch_config(b, bl, pp, bc))) break;
-        const BatchLaunch L = batch_launch(b);
-        hipError_t e = launch_batch_rk2(L, nullptr);  // warm-up
-        if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
-        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_batch_rk2(L, nullptr);
-        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-          st = hip_fail(e, "tuning run");
-          break;
-        }
-        if (ms / 3 < best.ms) best = TuneEntry{bl, pp, bc, ms / 3.0};
+        if (st) break;
+        TuneEntry c{bl, pp, bc, 0.0};
+        if (!(st = time_shape(c, 3, &c.ms))) timed.push_back(c);
       }
+  // pass 2: the four fastest and the shape in use, 10 launches each, twice in
+  // turn; keep each one's better time
+  TuneEntry best = current;
+  best.ms = 1e30;
+  if (!st) {
+    std::sort(timed.begin(), timed.end(),
+              [](const TuneEntry& x, const TuneEntry& y) { return x.ms < y.ms; });
+    std::vector<TuneEntry> finalists(timed.begin(), timed.begin() + std::min<size_t>(4, timed.size()));
+    finalists.push_back(current);
+    for (TuneEntry& c : finalists) c.ms = 1e30;
+    for (int round = 0; round < 2 && !st; ++round)
+      for (TuneEntry& c : finalists) {
+        double ms = 0.0;
+        if ((st = time_shape(c, 10, &ms))) break;
+        c.ms = std::min(c.ms, ms);
+      }
+    for (const TuneEntry& c : finalists)
+      if (c.ms < best.ms) best = c;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   soax_status rst = snapshot(b, snap, true);

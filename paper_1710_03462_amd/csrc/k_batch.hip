@@ -3,10 +3,11 @@
 // amplitudes.
 //
 // The sets are cut into tiles of `tile` particles (the last tile of a set may
-// be short) and listed back to back; a grid of a few workgroups per compute
-// unit walks the list with a grid stride, reading each tile's set from a
-// device table.  Small sets therefore share the machine instead of each
-// paying for a launch of its own.  The per-particle arithmetic is the same
+// be short) and listed back to back; each workgroup reads its tile's set from
+// a device table.  Either every tile has a workgroup of its own, or a grid of
+// a few workgroups per compute unit walks the list with a grid stride.  Small
+// sets therefore share the machine instead of each paying for a launch of its
+// own.  The per-particle arithmetic is the same
 // inline function the single-set kernels use, so a set advanced here is
 // bit-identical to the same set advanced alone.
 #include <hip/hip_runtime.h>
@@ -80,18 +81,34 @@ __global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
   }
 }
 
+// The same with one workgroup per tile (the grid covers the tile list).
+// Without the grid-stride loop the kernel needs fewer registers (64 rather
+// than 80 at one particle per thread), so more waves stay resident.
+template <typename VT, int PPT>
+__global__ __launch_bounds__(512) void batch_rk2_tile_kernel(BatchLaunch b) {
+  const int64_t t = blockIdx.x;
+  if (t >= b.ntiles) return;
+  const BatchSet& S = b.sets[b.tile_set[t]];
+  if (S.small)
+    batch_tile<VT, PPT, true>(S, t, b.tile);
+  else
+    batch_tile<VT, PPT, false>(S, t, b.tile);
+}
+
+template <typename VT, int PPT>
+void batch_launch_ppt(const BatchLaunch& b, hipStream_t s) {
+  if (b.grid >= b.ntiles)
+    hipLaunchKernelGGL((batch_rk2_tile_kernel<VT, PPT>), dim3(b.ntiles), dim3(b.block), 0, s, b);
+  else
+    hipLaunchKernelGGL((batch_rk2_kernel<VT, PPT>), dim3(b.grid), dim3(b.block), 0, s, b);
+}
+
 template <typename VT>
 hipError_t batch_t(const BatchLaunch& b, hipStream_t s) {
   switch (b.per_thread) {
-    case 1:
-      hipLaunchKernelGGL((batch_rk2_kernel<VT, 1>), dim3(b.grid), dim3(b.block), 0, s, b);
-      break;
-    case 2:
-      hipLaunchKernelGGL((batch_rk2_kernel<VT, 2>), dim3(b.grid), dim3(b.block), 0, s, b);
-      break;
-    default:
-      hipLaunchKernelGGL((batch_rk2_kernel<VT, 4>), dim3(b.grid), dim3(b.block), 0, s, b);
-      break;
+    case 1: batch_launch_ppt<VT, 1>(b, s); break;
+    case 2: batch_launch_ppt<VT, 2>(b, s); break;
+    default: batch_launch_ppt<VT, 4>(b, s); break;
   }
   return hipGetLastError();
 }

@@ -93,7 +93,8 @@ def test_modes_and_single_sets_bit_identical():
 def test_launch_shape_does_not_change_results():
     dts, abc = plan(len(SIZES))
     base = None
-    for block, ppt, bpc in [(256, 2, 8), (64, 1, 1), (128, 4, 2), (512, 2, 16), (512, 4, 1)]:
+    for block, ppt, bpc in [(256, 1, 65536), (256, 2, 8), (64, 1, 1), (128, 4, 2), (512, 2, 16),
+                            (512, 4, 1), (128, 2, 65536)]:
         sets, _ = make_sets(SIZES)
         b = soax.Batch(sets)
         b.config(block, ppt, bpc)
@@ -129,7 +130,7 @@ def test_tuner_keeps_state_and_writes_cache(tmp_path):
     cfg = b.tune(cache)
     after = download(sets)
     assert same(before, after)
-    assert cfg[0] in (128, 256, 512) and cfg[1] in (1, 2, 4) and cfg[2] in (2, 4, 8, 16, 32, 64)
+    assert cfg[0] in (128, 256, 512) and cfg[1] in (1, 2, 4) and cfg[2] in (2, 4, 8, 16, 32, 64, 65536)
     assert os.path.exists(cache)
     text = open(cache).read()
     assert "batch_rk2" in text and f'"block": {cfg[0]}' in text
@@ -138,3 +139,14 @@ def test_tuner_keeps_state_and_writes_cache(tmp_path):
     b.step(dts, abc, 3, mode=soax.GRAPH)
     b2.step(dts, abc, 3, mode=soax.GRAPH)
     assert same(download(b.sets), download(b2.sets))
+
+
+def test_config_defaults_and_rejects_bad_shapes():
+    sets, _ = make_sets(SIZES[:3])
+    b = soax.Batch(sets)
+    # default: one tile per workgroup, one particle per thread
+    assert b.get_config() == (256, 1, 65536)
+    for block, ppt, bpc in [(100, 0, 0), (1024, 0, 0), (0, 3, 0), (0, 0, 65537), (0, 0, -1)]:
+        with pytest.raises(soax.SoaxError):
+            b.config(block, ppt, bpc)
+    assert b.get_config() == (256, 1, 65536)
