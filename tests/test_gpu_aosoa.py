@@ -21,9 +21,17 @@ def make(fields, n, seed, **kw):
     return ps, arrays
 
 
-@pytest.mark.parametrize("fields", [si.BASE_FIELDS, si.WIDE_FIELDS], ids=["base", "wide"])
+# arrays per element size (8, 4, 1 bytes): base 3/4/0, wide 4/8/1,
+# bytes 1/2/4, particle5 0/11/0 -- every remainder of the 4-array blocks
+XFIELDS = {"base": si.BASE_FIELDS, "wide": si.WIDE_FIELDS,
+           "bytes": [("a", "u8", 1), ("b", "i64", 1), ("c", "i8", 3), ("d", "f32", 2)],
+           "particle5": si.particle_size_fields(5)}
+
+
+@pytest.mark.parametrize("key", sorted(XFIELDS))
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 4099])
-def test_conversions_match_oracle_tiles(ref, fields, n):
+def test_conversions_match_oracle_tiles(ref, key, n):
+    fields = XFIELDS[key]
     ps, arrays = make(fields, n, n)
     ps.soa_to_aosoa()
     torch.cuda.synchronize()
