@@ -22,73 +22,96 @@ constexpr int kBlock = 256;
 constexpr int kItems = 16;  // elements per thread per tile
 constexpr int64_t kTile = int64_t(kBlock) * kItems;
 
-__global__ __launch_bounds__(kBlock) void count_flags_kernel(const uint8_t* __restrict__ flags,
-                                                             int64_t n,
-                                                             int32_t* __restrict__ counts) {
-  __shared__ int32_t red[kBlock];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + threadIdx.x * kItems;
-  int32_t c = 0;
-#pragma unroll
+// Bit j (0..3) set iff byte j of w is nonzero: adding 0x7F to the low seven
+// bits of a byte carries into its bit 7 iff they are not all zero, and no
+// carry leaves the byte.
+__device__ __forceinline__ uint32_t nonzero_bytes4(uint32_t w) {
+  const uint32_t hi = (((w & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w) & 0x80808080u;
+  return ((hi >> 7) & 1u) | ((hi >> 14) & 2u) | ((hi >> 21) & 4u) | ((hi >> 28) & 8u);
+}
+
+// Bit j set iff element base + j (j < kItems) is in range and flagged.  A
+// whole in-range run of 16-byte aligned flags is one 16-byte load; the last
+// run of the array, or unaligned flags, go byte by byte so nothing past n is
+// read.
+__device__ __forceinline__ uint32_t flag_bits(const uint8_t* __restrict__ flags, int64_t base,
+                                              int64_t n, bool vec) {
+  static_assert(kItems == 16, "one 16-byte load per thread");
+  if (vec && base + kItems <= n) {
+    const uint4 w = *reinterpret_cast<const uint4*>(flags + base);
+    return nonzero_bytes4(w.x) | (nonzero_bytes4(w.y) << 4) | (nonzero_bytes4(w.z) << 8) |
+           (nonzero_bytes4(w.w) << 12);
+  }
+  uint32_t f = 0;
   for (int j = 0; j < kItems; ++j) {
     const int64_t i = base + j;
-    if (i < n && flags[i]) ++c;
+    if (i < n && flags[i]) f |= 1u << j;
   }
-  red[threadIdx.x] = c;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
+  return f;
+}
+
+// Inclusive scan of v over one 64-lane wave.
+__device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v) {
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
   }
-  if (threadIdx.x == 0) counts[blockIdx.x] = red[0];
+  return v;
 }
 
 // Exclusive scan of v over the workgroup; returns this thread's prefix and
-// writes the total to *total.
+// writes the total to *total.  Wave scans, then the wave totals through LDS.
 __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* total) {
-  __shared__ int32_t sc[kBlock];
-  sc[threadIdx.x] = v;
+  constexpr int kWaves = kBlock / 64;
+  __shared__ int32_t wave_sum[kWaves];
+  const int wid = static_cast<int>(threadIdx.x) >> 6;
+  const int32_t incl = wave_inclusive_scan(v);
+  if ((threadIdx.x & 63) == 63) wave_sum[wid] = incl;
   __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const int32_t add = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
-    __syncthreads();
-    sc[threadIdx.x] += add;
-    __syncthreads();
+  int32_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const int32_t t = wave_sum[w];
+    before += w < wid ? t : 0;
+    all += t;
   }
-  const int32_t incl = sc[threadIdx.x];
-  *total = sc[kBlock - 1];
-  __syncthreads();
-  return incl - v;
+  *total = all;
+  __syncthreads();  // wave_sum may be reused by the caller's next scan
+  return before + incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void count_flags_kernel(const uint8_t* __restrict__ flags,
+                                                             int64_t n, int vec,
+                                                             int32_t* __restrict__ counts) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + threadIdx.x * kItems;
+  int32_t total;
+  block_exclusive_scan(__popc(flag_bits(flags, base, n, vec)), &total);
+  if (threadIdx.x == 0) counts[blockIdx.x] = total;
 }
 
 // holes_before[b]: flagged slots in tiles before b; movers_after[b]:
 // unflagged particles in tiles after b -- both from the host's scan of the
-// counts.  Each thread walks its kItems elements in order, so ranks inside a
-// tile come from two workgroup scans.
+// counts.  Each thread walks its kItems elements in order; one workgroup
+// scan of the flagged counts gives both ranks inside the tile, because every
+// thread before this one holds kItems in-range elements or the tile's last.
 __global__ __launch_bounds__(kBlock) void rank_kernel(const uint8_t* __restrict__ flags, int64_t n,
-                                                      int64_t n_new,
+                                                      int vec, int64_t n_new,
                                                       const int64_t* __restrict__ holes_before,
                                                       const int64_t* __restrict__ movers_after,
                                                       int64_t* __restrict__ hole_at,
                                                       int64_t* __restrict__ mover_at,
                                                       int64_t* __restrict__ nmoves) {
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + threadIdx.x * kItems;
-  uint32_t f = 0;  // bit j: element base + j is flagged (in-range elements only)
-  int32_t nf = 0, nu = 0;
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = base + j;
-    if (i < n) {
-      if (flags[i]) {
-        f |= 1u << j;
-        ++nf;
-      } else {
-        ++nu;
-      }
-    }
-  }
-  int32_t tot_f, tot_u;
-  const int32_t pre_f = block_exclusive_scan(nf, &tot_f);
-  const int32_t pre_u = block_exclusive_scan(nu, &tot_u);
+  const int64_t tile0 = static_cast<int64_t>(blockIdx.x) * kTile;
+  const int64_t base = tile0 + threadIdx.x * kItems;
+  const uint32_t f = flag_bits(flags, base, n, vec);
+  int32_t tot_f;
+  const int32_t pre_f = block_exclusive_scan(__popc(f), &tot_f);
+  const int64_t in_tile = min(kTile, n - tile0);
+  const int32_t in_before = static_cast<int32_t>(min(static_cast<int64_t>(threadIdx.x) * kItems, in_tile));
+  const int32_t pre_u = in_before - pre_f;  // unflagged elements before this thread's
+  const int32_t tot_u = static_cast<int32_t>(in_tile) - tot_f;
   int64_t hole = holes_before[blockIdx.x] + pre_f;  // flagged slots before element i
   int32_t upto_u = pre_u;                           // unflagged in the tile up to element i
 #pragma unroll
@@ -169,9 +192,14 @@ int64_t container_tile_size() { return kTile; }
 
 int64_t container_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
 
+// 16-byte loads of the flags need a 16-byte aligned array.
+static int flags_vec(const uint8_t* flags) { return (reinterpret_cast<uintptr_t>(flags) & 15u) == 0; }
+
 hipError_t launch_count_flags(const uint8_t* flags, int64_t n, int32_t* counts, hipStream_t s) {
   const int64_t grid = container_tiles(n);
-  if (grid > 0) hipLaunchKernelGGL(count_flags_kernel, dim3(grid), dim3(kBlock), 0, s, flags, n, counts);
+  if (grid > 0)
+    hipLaunchKernelGGL(count_flags_kernel, dim3(grid), dim3(kBlock), 0, s, flags, n,
+                       flags_vec(flags), counts);
   return hipGetLastError();
 }
 
@@ -180,8 +208,8 @@ hipError_t launch_rank_flags(const uint8_t* flags, int64_t n, int64_t n_new,
                              int64_t* hole_at, int64_t* mover_at, int64_t* nmoves, hipStream_t s) {
   const int64_t grid = container_tiles(n);
   if (grid > 0)
-    hipLaunchKernelGGL(rank_kernel, dim3(grid), dim3(kBlock), 0, s, flags, n, n_new, holes_before,
-                       movers_after, hole_at, mover_at, nmoves);
+    hipLaunchKernelGGL(rank_kernel, dim3(grid), dim3(kBlock), 0, s, flags, n, flags_vec(flags),
+                       n_new, holes_before, movers_after, hole_at, mover_at, nmoves);
   return hipGetLastError();
 }
 

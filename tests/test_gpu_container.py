@@ -253,3 +253,25 @@ def test_element_access_like_get_element():
     ps.push_back(e2.tobytes())
     assert ps.n == 51 and int(ps.element(50)["id"]) == 50
     ps.close()
+
+
+@pytest.mark.parametrize("offset", [0, 1, 8])
+def test_remove_flag_bytes_and_alignment(ref, offset):
+    # any nonzero byte flags a particle; flags that do not start on a 16-byte
+    # boundary, and a flags tensor longer than n, give the same result
+    fields, packed = SCHEMAS["base"]
+    n = 40_003
+    ps, arrays = make_set(fields, packed, n, 21)
+    rng = np.random.default_rng(21)
+    vals = np.array([1, 2, 0x40, 0x7F, 0x80, 0xFF], np.uint8)
+    flags = np.where(rng.random(n) < 0.05, rng.choice(vals, n), 0).astype(np.uint8)
+    buf = torch.zeros(n + offset + 37, dtype=torch.uint8, device="cuda")
+    buf[offset: offset + n] = torch.from_numpy(flags).cuda()
+    buf[offset + n:] = 1  # past n: never read as flags
+    want, m = ref.remove_flagged(ref.Schema(fields, packed), arrays, (flags != 0).astype(np.uint8))
+    assert ps.remove_flagged(buf[offset:]) == m
+    torch.cuda.synchronize()
+    for g, w in zip(ps.download_soa(), want):
+        assert np.array_equal(g.view(np.uint8), w.view(np.uint8))
+    assert np.array_equal(ps.download_aos(), to_aos(fields, want, packed))
+    ps.close()
