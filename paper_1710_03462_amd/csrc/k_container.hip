@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "launch.h"
 
 namespace soax {
@@ -181,9 +183,15 @@ __global__ __launch_bounds__(kBlock) void move_all_kernel(MoveArgs a,
   }
 }
 
-__global__ __launch_bounds__(256) void zero_kernel(char* __restrict__ p, int64_t bytes) {
+// Zero `bytes` bytes at p: single bytes up to the first 16-byte boundary,
+// 16-byte stores for the aligned body, single bytes for the rest.
+__global__ __launch_bounds__(256) void zero_kernel(char* __restrict__ p, int64_t head,
+                                                   int64_t nbody, int64_t bytes) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < bytes) p[i] = 0;
+  if (i < head) p[i] = 0;
+  if (i < nbody) reinterpret_cast<uint4*>(p + head)[i] = make_uint4(0u, 0u, 0u, 0u);
+  const int64_t tail0 = head + (nbody << 4);
+  if (i < bytes - tail0) p[tail0 + i] = 0;
 }
 
 }  // namespace
@@ -228,8 +236,14 @@ hipError_t launch_move_all(const MoveArgs& m, const int64_t* hole_at, const int6
 
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s) {
   if (bytes <= 0) return hipSuccess;
-  const int64_t grid = (bytes + 255) / 256;
-  hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(256), 0, s, static_cast<char*>(p), bytes);
+  const int64_t mis = static_cast<int64_t>(reinterpret_cast<uintptr_t>(p) & 15u);
+  const int64_t head = std::min(bytes, (16 - mis) & 15);
+  const int64_t nbody = (bytes - head) >> 4;
+  const int64_t tail = bytes - head - (nbody << 4);  // < 16
+  const int64_t threads = std::max(nbody, std::max(head, tail));
+  const int64_t grid = (threads + 255) / 256;
+  hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(256), 0, s, static_cast<char*>(p), head, nbody,
+                     bytes);
   return hipGetLastError();
 }
 
