@@ -23,3 +23,14 @@ def ref():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def host_lib():
+    """libsoax.so for the CPU-only C-ABI tests, compiled here first if this
+    checkout has not been built (hipcc cross-compiles for gfx950 without a
+    GPU).  GPU tests load the library that was built beforehand."""
+    from paper_1710_03462_amd import _lib, build
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    return _lib.lib()

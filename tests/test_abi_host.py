@@ -18,8 +18,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module")
-def L():
-    return _lib.lib()
+def L(host_lib):
+    return host_lib
 
 
 def test_exports_every_declared_function(L):
@@ -241,13 +241,13 @@ def test_bind_capacity_validation(L):
     L.soax_destroy(h)
 
 
-def test_aosoa_layout_agrees_with_oracle(ref):
+def test_aosoa_layout_agrees_with_oracle(ref, L):
     for fields in SCHEMAS:
         sch, keep = _lib.make_schema(fields)
         narr = sum(int(f[2]) for f in fields)
         off = (ctypes.c_int64 * narr)()
         tile = ctypes.c_int64()
-        assert _lib.lib().soax_aosoa_layout(ctypes.byref(sch), off, ctypes.byref(tile)) == 0
+        assert L.soax_aosoa_layout(ctypes.byref(sch), off, ctypes.byref(tile)) == 0
         roff, rtile = ref.aosoa_layout(ref.Schema(fields))
         assert (list(off), tile.value) == (roff, rtile)
 
@@ -269,7 +269,7 @@ def test_product_fails_loudly_without_the_library(tmp_path):
     assert "raised: True" in r.stdout, r.stdout + r.stderr
 
 
-def test_product_never_imports_the_oracle():
+def test_product_never_imports_the_oracle(host_lib):
     import subprocess
     import sys
     code = ("import sys, paper_1710_03462_amd as s\n"

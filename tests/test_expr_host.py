@@ -14,6 +14,11 @@ from paper_1710_03462_amd import expr as E  # noqa: E402
 E_ARG, E_SCHEMA = -1, -2
 
 
+@pytest.fixture(autouse=True)
+def _built(host_lib):
+    """Every test here calls the library through _lib.lib()."""
+
+
 def prog(*ops):
     arr = (E.ExprOp * len(ops))()
     for i, o in enumerate(ops):
