@@ -19,8 +19,9 @@
 // their Taylor series (truncated after d^5 and d^6; omitted terms below
 // 5e-17 absolute).  A time step moves a particle by dt*u, far less than 1/64
 // for the step sizes of interest, so the midpoint and end-point values of a
-// step come from the start-point values without a second reduction; larger
-// shifts fall back to sincos_fast(x + d).  The shift uses the exact sum x + d, which differs from
+// step come from the start-point values without a second reduction.  The
+// checked form also takes shifts up to 1/8, with series truncated after d^9
+// and d^10; larger shifts fall back to sincos_fast(x + d).  The shift uses the exact sum x + d, which differs from
 // the rounded sum by at most half an ulp of x.
 //
 // Every result is within about one ulp of the exact value (checked against
@@ -117,20 +118,32 @@ __host__ __device__ __forceinline__ void sincos_fast(double x, double* s, double
 constexpr double T1 = -inv_fact(3), T2 = inv_fact(5);
 // cos d - 1 = w (-1/2 + w (U1 + w U2))
 constexpr double U1 = inv_fact(4), U2 = -inv_fact(6);
+// the longer series of the checked form for 1/64 < |d| <= 1/8:
+// sin d = d + d^3 (T1 + w (T2 + w (T3 + w T4))), omitted terms below 3e-18;
+// cos d - 1 = w (-1/2 + w (U1 + w (U2 + w (U3 + w U4)))), below 3e-20
+constexpr double kShiftLong = 1.0 / 8;
+constexpr double T3 = -inv_fact(7), T4 = inv_fact(9);
+constexpr double U3 = inv_fact(8), U4 = -inv_fact(10);
 
-// CHECKED = false: the caller guarantees |d| <= kShiftMax.
+// CHECKED = false: the caller guarantees |d| <= kShiftMax.  CHECKED = true:
+// any d; 1/64 < |d| <= 1/8 takes the longer series, larger shifts a full
+// reduction of x + d.
 template <bool CHECKED = true>
 __host__ __device__ __forceinline__ void sincos_shift(double x, double sx, double cx, double d,
                                                       double* s, double* c) {
-  if constexpr (CHECKED) {
-    if (!(fabs(d) <= kShiftMax)) {
+  double sd, cm1;
+  const double w = d * d;
+  if (CHECKED && !(fabs(d) <= kShiftMax)) {
+    if (!(fabs(d) <= kShiftLong)) {
       sincos_fast(x + d, s, c);
       return;
     }
+    sd = fma(d * w, fma(w, fma(w, w * T4 + T3, T2), T1), d);
+    cm1 = w * fma(w, fma(w, fma(w, w * U4 + U3, U2), U1), -0.5);
+  } else {
+    sd = fma(d * w, w * T2 + T1, d);
+    cm1 = w * fma(w, w * U2 + U1, -0.5);
   }
-  const double w = d * d;
-  const double sd = fma(d * w, w * T2 + T1, d);
-  const double cm1 = w * fma(w, w * U2 + U1, -0.5);
   // sin(x+d) = sin x + (sin x (cos d - 1) + cos x sin d), likewise for cos
   *s = fma(cx, sd, fma(sx, cm1, sx));
   *c = fma(-sx, sd, fma(cx, cm1, cx));

@@ -33,3 +33,25 @@ def test_sincos_within_two_ulp_of_glibc(exe, lo, hi):
     assert worst_c <= 2.0, out
     if hi - lo < 1e3:  # the shifted form: absolute error in units of ulp(1)
         assert shift_s <= 1.0 and shift_c <= 1.0, out
+
+
+@pytest.mark.parametrize("lo,hi", [(-1.0, 8.0), (-20.0, 20.0), (-1e-3, 1e-3)])
+def test_checked_shift_longer_series_within_one_ulp(exe, lo, hi):
+    # shifts up to 1/8: the checked form's degree-9/10 series keeps the
+    # absolute error of sin/cos(x + d) within one ulp of 1
+    out = subprocess.run([exe, str(lo), str(hi), "400000", str(1.0 / 8)], check=True,
+                         capture_output=True, text=True).stdout.split()
+    assert float(out[4]) <= 1.0 and float(out[5]) <= 1.0, out
+
+
+@pytest.mark.parametrize("lo,hi", [(-1.0, 8.0), (-20.0, 20.0)])
+def test_checked_shift_full_reduction_beyond_the_series(exe, lo, hi):
+    # shifts up to 1/2 reach the full reduction of the rounded sum x + d: its
+    # error is at most half an ulp of x + d (the rounding of the sum) plus the
+    # reduction's own, in units of ulp(1)
+    import math
+    out = subprocess.run([exe, str(lo), str(hi), "400000", "0.5"], check=True,
+                         capture_output=True, text=True).stdout.split()
+    top = max(abs(lo), abs(hi)) + 0.5
+    bound = 1.0 + 0.5 * math.ulp(top) / 2.0 ** -52 + 1.0
+    assert float(out[4]) <= bound and float(out[5]) <= bound, (out, bound)

@@ -17,6 +17,10 @@ int main(int argc, char** argv) {
   const double lo = argc > 1 ? atof(argv[1]) : -1.0;
   const double hi = argc > 2 ? atof(argv[2]) : 8.0;
   const long n = argc > 3 ? atol(argv[3]) : 1000000;
+  // shifts of the shifted evaluation: |d| < shift_max (default 1/64, the
+  // bound of the unchecked form); larger values reach the checked form's
+  // longer series (to 1/8) and its full reduction
+  const double shift_max = argc > 4 ? atof(argv[4]) : 1.0 / 64;
   uint64_t st = 0x9E3779B97F4A7C15ull;
   double worst_s = 0, worst_c = 0, at_s = 0, at_c = 0;
   for (long i = 0; i < n + 16; ++i) {
@@ -51,8 +55,8 @@ int main(int argc, char** argv) {
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     const double x = lo + (hi - lo) * ((z >> 11) * 0x1p-53);
-    // shifts up to the bound of the unchecked form, 1/64 (a few much smaller)
-    const double d = ((z & 0x7ff) ? 0x1p-5 : 0x1p-10) * (((z >> 11) & 0xfffff) * 0x1p-20 - 0.5);
+    // shifts up to shift_max (a few much smaller)
+    const double d = ((z & 0x7ff) ? 2 * shift_max : 0x1p-10) * (((z >> 11) & 0xfffff) * 0x1p-20 - 0.5);
     double s, c, s2, c2;
     soax::trig::sincos_fast(x, &s, &c);
     soax::trig::sincos_shift(x, s, c, d, &s2, &c2);
