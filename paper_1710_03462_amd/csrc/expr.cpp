@@ -45,6 +45,16 @@ const char* ctype(int32_t t) {
   }
 }
 
+// Each thread evaluates two elements a block-width apart: both elements'
+// loads, then both elements' arithmetic, then both stores.  A thread alone
+// reads and writes its two elements, so a destination that is also a source
+// is still read before it is written.  Past the end of the array the second
+// element is element i0 again (loaded and stored with the first one's value),
+// so no load or store sits behind a branch: the compiler would otherwise sink
+// the second element's loads below the first element's store.
+constexpr int kExprBlock = 256;
+constexpr int kExprPerThread = 2;
+
 // Straight-line source of one program; `consts` receives the constant values
 // in the order the source refers to them.
 std::string generate(const ExprPlan& p, std::vector<double>* consts) {
@@ -52,66 +62,92 @@ std::string generate(const ExprPlan& p, std::vector<double>* consts) {
   char buf[256];
   s += "struct Args { const void* src[" + std::to_string(kExprMaxSrc) +
        "]; void* dst; long long n; double c[" + std::to_string(kExprMaxConst) + "]; };\n";
-  s += "extern \"C\" __global__ void __launch_bounds__(256) soax_expr_kernel(Args a) {\n";
-  s += "  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;\n";
-  s += "  if (i >= a.n) return;\n";
+  s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(kExprBlock) +
+       ") soax_expr_kernel(Args a) {\n";
+  s += "  const long long i0 = (long long)blockIdx.x * " + std::to_string(kExprBlock * kExprPerThread) +
+       " + threadIdx.x;\n";
+  s += "  if (i0 >= a.n) return;\n";
+  s += "  const long long i1 = i0 + " + std::to_string(kExprBlock) + ";\n";
+  s += "  const bool has1 = i1 < a.n;\n";
+  s += "  const long long j1 = has1 ? i1 : i0;\n";
   std::vector<bool> used(kExprMaxSrc, false);
   for (int k = 0; k < p.nops; ++k)
     if (p.ops[k].op == kOpArray) used[p.ops[k].arg] = true;
-  for (int j = 0; j < p.nsrc; ++j) {
-    if (!used[j]) continue;
-    const char* t = ctype(p.src_t[j]);
+  for (int e = 0; e < kExprPerThread; ++e)
+    for (int j = 0; j < p.nsrc; ++j) {
+      if (!used[j]) continue;
+      const char* t = ctype(p.src_t[j]);
+      const char* idx = e == 0 ? "i0" : "j1";
+      if (p.stream)
+        snprintf(buf, sizeof buf,
+                 "  const double s%d_%d = (double)__builtin_nontemporal_load((const %s*)a.src[%d] + %s);\n",
+                 j, e, t, j, idx);
+      else
+        snprintf(buf, sizeof buf, "  const double s%d_%d = (double)((const %s*)a.src[%d])[%s];\n", j, e, t,
+                 j, idx);
+      s += buf;
+    }
+  // constant k of the program is a.c[cidx[k]]
+  std::vector<int> cidx(p.nops, -1);
+  for (int k = 0; k < p.nops; ++k)
+    if (p.ops[k].op == kOpConst) {
+      cidx[k] = static_cast<int>(consts->size());
+      consts->push_back(p.ops[k].value);
+    }
+  const char* dt = ctype(p.dst_t);
+  std::string result[kExprPerThread];
+  for (int el = 0; el < kExprPerThread; ++el) {
+    const std::string sfx = "_" + std::to_string(el);
+    std::vector<std::string> stack;
+    for (int k = 0; k < p.nops; ++k) {
+      const ExprOp& o = p.ops[k];
+      const std::string v = "t" + std::to_string(k) + sfx;
+      if (o.op == kOpArray) {
+        stack.push_back("s" + std::to_string(o.arg) + sfx);
+        continue;
+      }
+      if (o.op == kOpConst) {
+        stack.push_back("a.c[" + std::to_string(cidx[k]) + "]");
+        continue;
+      }
+      std::string e;
+      if (o.op == kOpNeg || o.op == kOpAbs || o.op == kOpSqrt) {
+        const std::string x = stack.back();
+        stack.pop_back();
+        if (o.op == kOpNeg) e = "-(" + x + ")";
+        else if (o.op == kOpAbs) e = "__builtin_fabs(" + x + ")";
+        else e = "__builtin_sqrt(" + x + ")";
+      } else {
+        const std::string b = stack.back();
+        stack.pop_back();
+        const std::string a = stack.back();
+        stack.pop_back();
+        switch (o.op) {
+          case kOpAdd: e = a + " + " + b; break;
+          case kOpSub: e = a + " - " + b; break;
+          case kOpMul: e = a + " * " + b; break;
+          case kOpDiv: e = a + " / " + b; break;
+          case kOpMin: e = "(" + a + " < " + b + " ? " + a + " : " + b + ")"; break;
+          default: e = "(" + a + " > " + b + " ? " + a + " : " + b + ")"; break;
+        }
+      }
+      s += "  const double " + v + " = " + e + ";\n";
+      stack.push_back(v);
+    }
+    result[el] = stack.back();
+  }
+  const std::string value[kExprPerThread] = {result[0],
+                                             "has1 ? " + result[1] + " : " + result[0]};
+  for (int el = 0; el < kExprPerThread; ++el) {
+    const char* idx = el == 0 ? "i0" : "j1";
     if (p.stream)
-      snprintf(buf, sizeof buf, "  const double s%d = (double)__builtin_nontemporal_load((const %s*)a.src[%d] + i);\n",
-               j, t, j);
+      snprintf(buf, sizeof buf, "  __builtin_nontemporal_store((%s)(%s), (%s*)a.dst + %s);\n", dt,
+               value[el].c_str(), dt, idx);
     else
-      snprintf(buf, sizeof buf, "  const double s%d = (double)((const %s*)a.src[%d])[i];\n", j, t, j);
+      snprintf(buf, sizeof buf, "  ((%s*)a.dst)[%s] = (%s)(%s);\n", dt, idx, dt, value[el].c_str());
     s += buf;
   }
-  std::vector<std::string> stack;
-  for (int k = 0; k < p.nops; ++k) {
-    const ExprOp& o = p.ops[k];
-    std::string v = "t" + std::to_string(k);
-    if (o.op == kOpArray) {
-      stack.push_back("s" + std::to_string(o.arg));
-      continue;
-    }
-    if (o.op == kOpConst) {
-      stack.push_back("a.c[" + std::to_string(consts->size()) + "]");
-      consts->push_back(o.value);
-      continue;
-    }
-    std::string e;
-    if (o.op == kOpNeg || o.op == kOpAbs || o.op == kOpSqrt) {
-      const std::string x = stack.back();
-      stack.pop_back();
-      if (o.op == kOpNeg) e = "-(" + x + ")";
-      else if (o.op == kOpAbs) e = "__builtin_fabs(" + x + ")";
-      else e = "__builtin_sqrt(" + x + ")";
-    } else {
-      const std::string b = stack.back();
-      stack.pop_back();
-      const std::string a = stack.back();
-      stack.pop_back();
-      switch (o.op) {
-        case kOpAdd: e = a + " + " + b; break;
-        case kOpSub: e = a + " - " + b; break;
-        case kOpMul: e = a + " * " + b; break;
-        case kOpDiv: e = a + " / " + b; break;
-        case kOpMin: e = "(" + a + " < " + b + " ? " + a + " : " + b + ")"; break;
-        default: e = "(" + a + " > " + b + " ? " + a + " : " + b + ")"; break;
-      }
-    }
-    s += "  const double " + v + " = " + e + ";\n";
-    stack.push_back(v);
-  }
-  const char* dt = ctype(p.dst_t);
-  if (p.stream)
-    snprintf(buf, sizeof buf, "  __builtin_nontemporal_store((%s)(%s), (%s*)a.dst + i);\n}\n", dt,
-             stack.back().c_str(), dt);
-  else
-    snprintf(buf, sizeof buf, "  ((%s*)a.dst)[i] = (%s)(%s);\n}\n", dt, dt, stack.back().c_str());
-  s += buf;
+  s += "}\n";
   return s;
 }
 
@@ -193,8 +229,9 @@ hipError_t launch_expr(const ExprPlan& p, hipStream_t s, std::string* log) {
   size_t size = sizeof a;
   void* config[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size,
                     HIP_LAUNCH_PARAM_END};
-  const unsigned grid = static_cast<unsigned>((p.n + 255) / 256);
-  return hipModuleLaunchKernel(c.fn, grid, 1, 1, 256, 1, 1, 0, s, nullptr, config);
+  const int64_t per_block = static_cast<int64_t>(kExprBlock) * kExprPerThread;
+  const unsigned grid = static_cast<unsigned>((p.n + per_block - 1) / per_block);
+  return hipModuleLaunchKernel(c.fn, grid, 1, 1, kExprBlock, 1, 1, 0, s, nullptr, config);
 }
 
 }  // namespace soax
