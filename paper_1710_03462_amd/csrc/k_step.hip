@@ -412,9 +412,9 @@ __device__ __forceinline__ void scatter_size(const XposeArgs& t, int b, int e, i
 }
 
 // AoS -> SoA: the tile's records are staged through LDS with coalesced 16-byte
-// loads; then, array by array (a loop uniform across the workgroup), thread r
-// moves element r from its record in LDS to the array, so consecutive lanes
-// store consecutive elements.
+// loads; then thread r moves every field of record r from LDS to element r of
+// its array, a block of arrays of one element size at a time (uniform across
+// the workgroup), so consecutive lanes store consecutive elements.
 template <bool ALIGNED, bool STREAM>
 __global__ __launch_bounds__(256) void aos_to_soa_kernel(const XposeArgs* __restrict__ tp,
                                                          int64_t n, int tile) {
@@ -435,8 +435,8 @@ __global__ __launch_bounds__(256) void aos_to_soa_kernel(const XposeArgs* __rest
 }
 
 // SoA -> AoS: zero the LDS tile (padding bytes are whatever no field writes),
-// scatter every array's elements into their records, then store the tile with
-// coalesced 16-byte stores.
+// gather element r of every array into record r, a block of arrays of one
+// element size at a time, then store the tile with coalesced 16-byte stores.
 template <bool ALIGNED, bool STREAM>
 __global__ __launch_bounds__(256) void soa_to_aos_kernel(const XposeArgs* __restrict__ tp,
                                                          int64_t n, int tile) {
