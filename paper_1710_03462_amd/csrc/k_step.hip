@@ -501,13 +501,15 @@ __device__ __forceinline__ void aosoa_size(const XposeArgs& t, int b, int e, cha
   });
 }
 
-// SoA <-> AoSoA: one thread per particle lane; the 64 lanes of a wave cover
-// one tile, so both sides of every copy are contiguous runs.
+// SoA <-> AoSoA: one thread per particle lane from lane `first` on; the 64
+// lanes of a wave cover one tile, so both sides of every copy are contiguous
+// runs.  Used for the last, partial tile, and for every tile when an array
+// is not 16-byte aligned.
 template <bool TO_SOA>
 __global__ __launch_bounds__(256) void aosoa_xpose_kernel(const XposeArgs* __restrict__ tp,
-                                                          int64_t n) {
+                                                          int64_t n, int64_t first) {
   const XposeArgs& t = *tp;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t i = first + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t lanes = (n + kAosoaW - 1) / kAosoaW * kAosoaW;
   if (i >= lanes) return;
   char* tile = t.aos + (i / kAosoaW) * t.stride;
@@ -515,6 +517,28 @@ __global__ __launch_bounds__(256) void aosoa_xpose_kernel(const XposeArgs* __res
   aosoa_size<uint64_t, TO_SOA>(t, 0, t.group_end[0], tile, lane, i, n);
   aosoa_size<uint32_t, TO_SOA>(t, t.group_end[0], t.group_end[1], tile, lane, i, n);
   aosoa_size<uint8_t, TO_SOA>(t, t.group_end[1], t.group_end[2], tile, lane, i, n);
+}
+
+// SoA <-> AoSoA for the `full` whole tiles: each array's 64 elements form
+// one 16-byte aligned run on both sides (a tile holds no padding and every
+// array starts at a multiple of 64 bytes), so thread g copies 16-byte chunk
+// g % chunks of tile g / chunks.  Needs 16-byte aligned SoA arrays.
+template <bool TO_SOA>
+__global__ __launch_bounds__(256) void aosoa_chunk_kernel(const XposeArgs* __restrict__ tp,
+                                                          int64_t full, int32_t chunks) {
+  const XposeArgs& t = *tp;
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= full * chunks) return;
+  const int64_t tile = g / chunks;
+  const int32_t byte = static_cast<int32_t>(g - tile * chunks) * 16;
+  int a = 0;  // the array whose run holds this chunk (offsets ascend)
+  for (int k = 1; k < t.narrays; ++k)
+    if (t.off[k] <= byte) a = k;
+  const int64_t run = static_cast<int64_t>(kAosoaW) * t.es[a];
+  u32x4* tile_p = reinterpret_cast<u32x4*>(t.aos + tile * t.stride + byte);
+  u32x4* soa_p = reinterpret_cast<u32x4*>(t.soa[a] + tile * run + (byte - t.off[a]));
+  if constexpr (TO_SOA) *soa_p = *tile_p;
+  else *tile_p = *soa_p;
 }
 
 template <int INTEG, typename PT, typename VT, bool SMALL, bool STREAM>
@@ -778,11 +802,27 @@ hipError_t launch_aosoa_xpose(bool to_soa, const XposeArgs& host, const XposeArg
                               hipStream_t s) {
   if (host.n == 0) return hipSuccess;
   const int64_t lanes = (host.n + kAosoaW - 1) / kAosoaW * kAosoaW;
-  const int64_t grid = (lanes + 255) / 256;
-  if (to_soa)
-    hipLaunchKernelGGL(aosoa_xpose_kernel<true>, dim3(grid), dim3(256), 0, s, dev, host.n);
-  else
-    hipLaunchKernelGGL(aosoa_xpose_kernel<false>, dim3(grid), dim3(256), 0, s, dev, host.n);
+  bool aligned = true;  // whole tiles go by 16-byte chunks when every array allows it
+  for (int a = 0; a < host.narrays; ++a)
+    if (reinterpret_cast<uintptr_t>(host.soa[a]) & 15u) aligned = false;
+  int64_t first = 0;
+  const int64_t full = host.n / kAosoaW;
+  if (aligned && full > 0 && host.stride % 16 == 0) {
+    const int32_t chunks = host.stride / 16;
+    const int64_t grid = (full * chunks + 255) / 256;
+    if (to_soa)
+      hipLaunchKernelGGL(aosoa_chunk_kernel<true>, dim3(grid), dim3(256), 0, s, dev, full, chunks);
+    else
+      hipLaunchKernelGGL(aosoa_chunk_kernel<false>, dim3(grid), dim3(256), 0, s, dev, full, chunks);
+    first = full * kAosoaW;
+  }
+  if (first < lanes) {
+    const int64_t grid = (lanes - first + 255) / 256;
+    if (to_soa)
+      hipLaunchKernelGGL(aosoa_xpose_kernel<true>, dim3(grid), dim3(256), 0, s, dev, host.n, first);
+    else
+      hipLaunchKernelGGL(aosoa_xpose_kernel<false>, dim3(grid), dim3(256), 0, s, dev, host.n, first);
+  }
   return hipGetLastError();
 }
 
