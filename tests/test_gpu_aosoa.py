@@ -117,3 +117,41 @@ def test_records_from_tiles_and_growth(ref):
     cur = [np.concatenate([a, b]) for a, b in zip(arrays, new)]
     assert np.array_equal(ps.download_aosoa(), ref.soa_to_aosoa(ref.Schema(fields), cur))
     ps.close()
+
+
+def test_conversions_with_unaligned_arrays(ref):
+    # SoA arrays 8 bytes (4 for 4-byte elements) past a 16-byte boundary:
+    # every tile, not only the last, goes through the per-lane kernel
+    import ctypes
+    from paper_1710_03462_amd import _lib
+    fields = si.BASE_FIELDS
+    n = 1000
+    arrays = si.random_state(fields, n, seed=12)
+    bufs = [torch.empty(n + 4, dtype=t, device="cuda")
+            for t in (torch.int32, *(torch.float64,) * 3, *(torch.float32,) * 3)]
+    views = []
+    for b, a in zip(bufs, arrays):
+        v = b[1:1 + n]
+        v.copy_(torch.from_numpy(a))
+        views.append(v)
+    assert all(v.data_ptr() % 16 for v in views)
+    L = _lib.lib()
+    sch, keep = _lib.make_schema(fields)
+    ptrs = (ctypes.c_void_p * 7)(*[v.data_ptr() for v in views])
+    h = ctypes.c_void_p()
+    _lib.check(L.soax_bind(ctypes.byref(sch), n, ptrs, None, ctypes.byref(h)), "bind")
+    tile = ctypes.c_int64()
+    _lib.check(L.soax_aosoa_layout(ctypes.byref(sch), None, ctypes.byref(tile)), "layout")
+    nbytes = (n + 63) // 64 * tile.value
+    buf = torch.full((nbytes,), 0xA5, dtype=torch.uint8, device="cuda")
+    _lib.check(L.soax_bind_aosoa(h, ctypes.c_void_p(buf.data_ptr()), nbytes), "bind_aosoa")
+    _lib.check(L.soax_soa_to_aosoa(h, soax.current_stream()), "soa_to_aosoa")
+    torch.cuda.synchronize()
+    assert np.array_equal(buf.cpu().numpy(), ref.soa_to_aosoa(ref.Schema(fields), arrays))
+    for v in views:
+        v.zero_()
+    _lib.check(L.soax_aosoa_to_soa(h, soax.current_stream()), "aosoa_to_soa")
+    torch.cuda.synchronize()
+    L.soax_destroy(h)
+    for g, w in zip(views, arrays):
+        assert np.array_equal(g.cpu().numpy().view(np.uint8), w.view(np.uint8))
