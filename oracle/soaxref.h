@@ -14,6 +14,12 @@
  *
  * Return value of every int routine: 0 on success, a negative code on bad
  * arguments (-1 argument, -2 schema).  Nothing aborts.
+ *
+ * Parity unpinned, by design: sin, cos, log and sqrt here are glibc's, and
+ * the GPU library evaluates its own, so field values, RK2/Heun/RK4
+ * positions and the Box-Muller normals of the fill agree with this oracle
+ * within the tests' tolerances, not bit for bit.  Every routine is otherwise
+ * pinned by the tests to values the paper or the mathematics fix.
  */
 #ifndef SOAXREF_H
 #define SOAXREF_H
