@@ -140,6 +140,7 @@ soax_status check_generations(const soax_batch* b) {
 soax_status per_set_step(soax_batch* b, const double* dt, const double* abc, hipStream_t s) {
   for (size_t i = 0; i < b->sets.size(); ++i) {
     soax_set* set = b->sets[i];
+    if (set->n == 0) continue;  // an empty set may have no SoA arrays at all
     const Layout& L = set->L;
     const int fp = L.find("pos"), fv = L.find("vel");
     SoaStepArgs a{};

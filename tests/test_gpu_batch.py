@@ -150,3 +150,21 @@ def test_config_defaults_and_rejects_bad_shapes():
         with pytest.raises(soax.SoaxError):
             b.config(block, ppt, bpc)
     assert b.get_config() == (256, 1, 65536)
+
+
+@pytest.mark.parametrize("mode", [soax.PER_SET, soax.PERSISTENT, soax.GRAPH])
+def test_empty_sets_in_a_batch(mode):
+    # empty sets, one of them without any SoA arrays, change nothing for the others
+    sizes = [5, 0, 1000, 0]
+    dts, abc = plan(len(sizes))
+    sets, _ = make_sets([5, 1000], seed=30)
+    empty_soa = soax.ParticleSet(si.BASE_FIELDS, 0)
+    empty_aos_only = soax.ParticleSet(si.BASE_FIELDS, 0, soa=False)
+    batch_sets = [sets[0], empty_aos_only, sets[1], empty_soa]
+    soax.Batch(batch_sets).step(dts, abc, 6, mode=mode)
+    got = download(sets)
+    alone, _ = make_sets([5, 1000], seed=30)
+    for s, k in ((alone[0], 0), (alone[1], 2)):
+        s.step("soa", "rk2_abc", dts[k], 6, abc=abc[k], wrap=True)
+    assert same(got, download(alone))
+    assert empty_soa.n == 0 and empty_aos_only.n == 0
