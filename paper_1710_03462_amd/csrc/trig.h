@@ -92,14 +92,14 @@ __host__ __device__ __forceinline__ void sincos_fast(double x, double* s, double
   r = fma(-k, kPio2Mid, r);
   r = fma(-k, kPio2Lo, r);
   const double w = r * r;
-  double ps = w * S7 + S6;  // the lowest-order rounding is far below the result's ulp
+  double ps = fma(w, S7, S6);
   ps = fma_k(w, ps, S5);
   ps = fma_k(w, ps, S4);
   ps = fma_k(w, ps, S3);
   ps = fma_k(w, ps, S2);
   ps = fma_k(w, ps, S1);
   const double sr = fma(r * w, ps, r);
-  double pc = w * C7 + C6;
+  double pc = fma(w, C7, C6);
   pc = fma_k(w, pc, C5);
   pc = fma_k(w, pc, C4);
   pc = fma_k(w, pc, C3);
@@ -138,11 +138,11 @@ __host__ __device__ __forceinline__ void sincos_shift(double x, double sx, doubl
       sincos_fast(x + d, s, c);
       return;
     }
-    sd = fma(d * w, fma(w, fma(w, w * T4 + T3, T2), T1), d);
-    cm1 = w * fma(w, fma(w, fma(w, w * U4 + U3, U2), U1), -0.5);
+    sd = fma(d * w, fma(w, fma(w, fma(w, T4, T3), T2), T1), d);
+    cm1 = w * fma(w, fma(w, fma(w, fma(w, U4, U3), U2), U1), -0.5);
   } else {
-    sd = fma(d * w, w * T2 + T1, d);
-    cm1 = w * fma(w, w * U2 + U1, -0.5);
+    sd = fma(d * w, fma(w, T2, T1), d);
+    cm1 = w * fma(w, fma(w, U2, U1), -0.5);
   }
   // sin(x+d) = sin x + (sin x (cos d - 1) + cos x sin d), likewise for cos
   *s = fma(cx, sd, fma(sx, cm1, sx));
