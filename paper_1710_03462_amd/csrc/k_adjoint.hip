@@ -66,24 +66,25 @@ __device__ __forceinline__ void rk2_reverse(const Abc& p, double dt, double x, d
   field_of(p, t, k0, k1, k2);
   const double h = 0.5 * dt;
   const Trig3 m = trig3_shift<SMALL>(t, x, y, z, h * k0, h * k1, h * k2);  // at xm
-  // J(xm)^T lam
-  const double t0 = (p.B * m.cx) * l1 - (p.B * m.sx) * l2;
-  const double t1 = (p.C * m.cy) * l2 - (p.C * m.sy) * l0;
-  const double t2 = (p.A * m.cz) * l0 - (p.A * m.sz) * l1;
-  const double m0 = dt * t0, m1 = dt * t1, m2 = dt * t2;
-  // G(xm)^T lam and G(x)^T mu
-  const double qa = m.sz * l0 + m.cz * l1, qb = m.sx * l1 + m.cx * l2, qc = m.cy * l0 + m.sy * l2;
-  const double ra = t.sz * m0 + t.cz * m1, rb = t.sx * m1 + t.cx * m2, rc = t.cy * m0 + t.sy * m2;
-  g0 = g0 + (dt * qa + h * ra);
-  g1 = g1 + (dt * qb + h * rb);
-  g2 = g2 + (dt * qc + h * rc);
-  // J(x)^T mu
-  const double s0 = (p.B * t.cx) * m1 - (p.B * t.sx) * m2;
-  const double s1 = (p.C * t.cy) * m2 - (p.C * t.sy) * m0;
-  const double s2 = (p.A * t.cz) * m0 - (p.A * t.sz) * m1;
-  l0 = l0 + m0 + h * s0;
-  l1 = l1 + m1 + h * s1;
-  l2 = l2 + m2 + h * s2;
+  // mu = dt J(xm)^T lam, each component an amplitude times one fused
+  // difference; dt is folded into the amplitudes
+  const double dA = dt * p.A, dB = dt * p.B, dC = dt * p.C;
+  const double m0 = dB * fma(m.cx, l1, -(m.sx * l2));
+  const double m1 = dC * fma(m.cy, l2, -(m.sy * l0));
+  const double m2 = dA * fma(m.cz, l0, -(m.sz * l1));
+  // g += dt G(xm)^T lam + (dt/2) G(x)^T mu
+  const double qa = fma(m.sz, l0, m.cz * l1), qb = fma(m.sx, l1, m.cx * l2),
+               qc = fma(m.cy, l0, m.sy * l2);
+  const double ra = fma(t.sz, m0, t.cz * m1), rb = fma(t.sx, m1, t.cx * m2),
+               rc = fma(t.cy, m0, t.sy * m2);
+  g0 = g0 + fma(dt, qa, h * ra);
+  g1 = g1 + fma(dt, qb, h * rb);
+  g2 = g2 + fma(dt, qc, h * rc);
+  // lam = lam+ + mu + (dt/2) J(x)^T mu, with dt/2 folded into the amplitudes
+  const double hA = h * p.A, hB = h * p.B, hC = h * p.C;
+  l0 = (l0 + m0) + hB * fma(t.cx, m1, -(t.sx * m2));
+  l1 = (l1 + m1) + hC * fma(t.cy, m2, -(t.sy * m0));
+  l2 = (l2 + m2) + hA * fma(t.cz, m0, -(t.sz * m1));
 }
 
 // Sum v over the workgroup (kRedBlock threads) in a fixed tree order.
