@@ -110,8 +110,11 @@ __host__ __device__ __forceinline__ void sincos_fast(double x, double* s, double
   const int q = static_cast<int>(k);
   const double a = (q & 1) ? cr : sr;
   const double b = (q & 1) ? sr : cr;
-  *s = (q & 2) ? -a : a;
-  *c = ((q + 1) & 2) ? -b : b;
+  // bit 1 of q (of q + 1 for the cosine) is the sign: moved to bit 63
+  const uint64_t fs = static_cast<uint64_t>(q & 2) << 62;
+  const uint64_t fc = static_cast<uint64_t>((q + 1) & 2) << 62;
+  *s = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, a) ^ fs);
+  *c = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, b) ^ fc);
 }
 
 // sin d = d + d^3 (T1 + w T2)
