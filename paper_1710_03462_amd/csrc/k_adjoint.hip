@@ -62,10 +62,10 @@ __device__ __forceinline__ void rk2_reverse(const Abc& p, double dt, double x, d
                                             double& l0, double& l1, double& l2, double& g0,
                                             double& g1, double& g2) {
   const Trig3 t = trig3(x, y, z);
-  double k0, k1, k2;
-  field_of(p, t, k0, k1, k2);
   const double h = 0.5 * dt;
-  const Trig3 m = trig3_shift<SMALL>(t, x, y, z, h * k0, h * k1, h * k2);  // at xm
+  double h0, h1, h2;  // (dt/2) u(x), as in the forward step
+  field_of(scaled(p, h), t, h0, h1, h2);
+  const Trig3 m = trig3_shift<SMALL>(t, x, y, z, h0, h1, h2);  // at xm
   // mu = dt J(xm)^T lam, each component an amplitude times one fused
   // difference; dt is folded into the amplitudes
   const double dA = dt * p.A, dB = dt * p.B, dC = dt * p.C;
