@@ -67,6 +67,20 @@ __host__ __device__ __forceinline__ double fma_k(double a, double b, double k) {
 #endif
 }
 
+// a*ks + kv with one rounding, ks and kv compile-time constants.  On the GPU
+// ks is the scalar-register operand and kv comes from a vector register that
+// a loop keeps loaded: the three-operand fma writes a fresh register, so kv
+// need not first be copied into the destination of a two-operand fma.
+__host__ __device__ __forceinline__ double fma_sk(double a, double ks, double kv) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(ks), "v"(kv));
+  return r;
+#else
+  return fma(a, ks, kv);
+#endif
+}
+
 struct SinCos {
   double s, c;
 };
@@ -92,14 +106,14 @@ __host__ __device__ __forceinline__ void sincos_fast(double x, double* s, double
   r = fma(-k, kPio2Mid, r);
   r = fma(-k, kPio2Lo, r);
   const double w = r * r;
-  double ps = fma(w, S7, S6);
+  double ps = fma_sk(w, S7, S6);
   ps = fma_k(w, ps, S5);
   ps = fma_k(w, ps, S4);
   ps = fma_k(w, ps, S3);
   ps = fma_k(w, ps, S2);
   ps = fma_k(w, ps, S1);
   const double sr = fma(r * w, ps, r);
-  double pc = fma(w, C7, C6);
+  double pc = fma_sk(w, C7, C6);
   pc = fma_k(w, pc, C5);
   pc = fma_k(w, pc, C4);
   pc = fma_k(w, pc, C3);
