@@ -54,36 +54,38 @@ constexpr double S1 = -inv_fact(3), S2 = inv_fact(5), S3 = -inv_fact(7), S4 = in
 constexpr double C1 = inv_fact(4), C2 = -inv_fact(6), C3 = inv_fact(8), C4 = -inv_fact(10),
                  C5 = inv_fact(12), C6 = -inv_fact(14), C7 = inv_fact(16);
 
-// a*b + k with one rounding, k a compile-time constant.  On the GPU the
-// constant is passed as a scalar-register operand of a three-operand fma, so
-// no vector register has to be loaded with it first.
-__host__ __device__ __forceinline__ double fma_k(double a, double b, double k) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  double r;
-  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(k));
-  return r;
-#else
-  return fma(a, b, k);
-#endif
-}
-
-// a*ks + kv with one rounding, ks and kv compile-time constants.  On the GPU
-// ks is the scalar-register operand and kv comes from a vector register that
-// a loop keeps loaded: the three-operand fma writes a fresh register, so kv
-// need not first be copied into the destination of a two-operand fma.
-__host__ __device__ __forceinline__ double fma_sk(double a, double ks, double kv) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  double r;
-  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(ks), "v"(kv));
-  return r;
-#else
-  return fma(a, ks, kv);
-#endif
-}
-
 struct SinCos {
   double s, c;
 };
+
+// The two series' Horner chains in w: ps = S1 + w (S2 + ... + w S7) and
+// pc = C1 + w (C2 + ... + w C7), each step one fma.  On the GPU both chains
+// run interleaved in one block of three-operand fmas (the top step's added
+// constant from a vector register, every other constant a scalar-register
+// operand): the compiler cannot see into separate asm statements and pads
+// each dependent pair of them with a wait, which one block does not need.
+__host__ __device__ __forceinline__ void sin_cos_series(double w, double& ps, double& pc) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm("v_fma_f64 %0, %2, %3, %4\n\t"
+      "v_fma_f64 %1, %2, %5, %6\n\t"
+      "v_fma_f64 %0, %2, %0, %7\n\t"
+      "v_fma_f64 %1, %2, %1, %8\n\t"
+      "v_fma_f64 %0, %2, %0, %9\n\t"
+      "v_fma_f64 %1, %2, %1, %10\n\t"
+      "v_fma_f64 %0, %2, %0, %11\n\t"
+      "v_fma_f64 %1, %2, %1, %12\n\t"
+      "v_fma_f64 %0, %2, %0, %13\n\t"
+      "v_fma_f64 %1, %2, %1, %14\n\t"
+      "v_fma_f64 %0, %2, %0, %15\n\t"
+      "v_fma_f64 %1, %2, %1, %16"
+      : "=&v"(ps), "=&v"(pc)
+      : "v"(w), "s"(S7), "v"(S6), "s"(C7), "v"(C6), "s"(S5), "s"(C5), "s"(S4), "s"(C4),
+        "s"(S3), "s"(C3), "s"(S2), "s"(C2), "s"(S1), "s"(C1));
+#else
+  ps = fma(w, fma(w, fma(w, fma(w, fma(w, fma(w, S7, S6), S5), S4), S3), S2), S1);
+  pc = fma(w, fma(w, fma(w, fma(w, fma(w, fma(w, C7, C6), C5), C4), C3), C2), C1);
+#endif
+}
 
 // Out-of-range arguments: kept out of line so the fast path stays small.  The
 // pair is returned by value so that the caller's results never have to live
@@ -106,19 +108,9 @@ __host__ __device__ __forceinline__ void sincos_fast(double x, double* s, double
   r = fma(-k, kPio2Mid, r);
   r = fma(-k, kPio2Lo, r);
   const double w = r * r;
-  double ps = fma_sk(w, S7, S6);
-  ps = fma_k(w, ps, S5);
-  ps = fma_k(w, ps, S4);
-  ps = fma_k(w, ps, S3);
-  ps = fma_k(w, ps, S2);
-  ps = fma_k(w, ps, S1);
+  double ps, pc;
+  sin_cos_series(w, ps, pc);
   const double sr = fma(r * w, ps, r);
-  double pc = fma_sk(w, C7, C6);
-  pc = fma_k(w, pc, C5);
-  pc = fma_k(w, pc, C4);
-  pc = fma_k(w, pc, C3);
-  pc = fma_k(w, pc, C2);
-  pc = fma_k(w, pc, C1);
   const double cr = fma(w, fma(w, pc, -0.5), 1.0);
   // x = k pi/2 + r:  sin x = (sr, cr, -sr, -cr)[k mod 4], cos x = (cr, -sr, -cr, sr)[k mod 4]
   const int q = static_cast<int>(k);
