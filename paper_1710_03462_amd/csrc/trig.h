@@ -113,14 +113,16 @@ __host__ __device__ __forceinline__ void sincos_fast(double x, double* s, double
   const double sr = fma(r * w, ps, r);
   const double cr = fma(w, fma(w, pc, -0.5), 1.0);
   // x = k pi/2 + r:  sin x = (sr, cr, -sr, -cr)[k mod 4], cos x = (cr, -sr, -cr, sr)[k mod 4]
-  const int q = static_cast<int>(k);
-  const double a = (q & 1) ? cr : sr;
-  const double b = (q & 1) ? sr : cr;
-  // bit 1 of q (of q + 1 for the cosine) is the sign: moved to bit 63
-  const uint64_t fs = static_cast<uint64_t>(q & 2) << 62;
-  const uint64_t fc = static_cast<uint64_t>((q + 1) & 2) << 62;
-  *s = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, a) ^ fs);
-  *c = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, b) ^ fc);
+  const uint32_t q = static_cast<uint32_t>(static_cast<int>(k));
+  // bit 0 of q (swap sr and cr) and bit 1 (the sine's sign) moved to bit 31;
+  // the cosine's sign is bit 1 of q + 1, i.e. bit 1 xor bit 0
+  const uint32_t odd = q << 31;
+  const uint32_t hs = (q << 30) & 0x80000000u;
+  const uint32_t hc = hs ^ odd;
+  const double a = odd ? cr : sr;
+  const double b = odd ? sr : cr;
+  *s = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, a) ^ (static_cast<uint64_t>(hs) << 32));
+  *c = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, b) ^ (static_cast<uint64_t>(hc) << 32));
 }
 
 // sin d = d + d^3 (T1 + w T2)
