@@ -388,6 +388,26 @@ soax_status soax_adjoint(const double* tape, const double* const* lamT, int64_t 
                          const double* abc, double dt, int64_t nsteps, int64_t k,
                          double* const* grad_x0, double* grad_abc, void* stream);
 
+/*
+ * soax_adjoint for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results, bit for bit, but the per-workgroup
+ * partial sums of dL/d(A,B,C) live in a fixed device array of 1 MiB that the
+ * library holds on every GPU it runs on until the process ends (its address
+ * is looked up once per device, on the first call there).  The call
+ * allocates nothing; the caller still provides every input and output.
+ * n may be at most SOAX_ADJOINT_NOALLOC_MAX_N (one partial of three doubles
+ * per 256 particles); larger n fails with SOAX_E_RANGE before any device
+ * call.  Every call on one GPU shares that array: calls that overlap in time
+ * on one GPU (different streams, or different host threads) race and give
+ * undefined gradients; serialise them, e.g. on one stream.  Errors: ARG,
+ * RANGE, STATE (device index beyond 63), HIP.
+ */
+#define SOAX_ADJOINT_NOALLOC_MAX_N 11184640
+soax_status soax_adjoint_noalloc(const double* tape, const double* const* lamT, int64_t n,
+                                 const double* abc, double dt, int64_t nsteps, int64_t k,
+                                 double* const* grad_x0, double* grad_abc, void* stream);
+
 /* loss = sum_i sum_d (xT - target)^2 into loss[0] (device) and
  * lamT = 2 (xT - target) (device; may be NULL); fixed-order reduction. */
 soax_status soax_sqdist_loss(const double* const* xT, const double* const* target, int64_t n,

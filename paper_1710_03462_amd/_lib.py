@@ -80,6 +80,7 @@ def lib():
         "soax_get_record": [vp, i32, i64, vp],
         "soax_rk2_forward_ckpt": [vp, vp, i64, vp, dbl, i64, i64, vp, vp],
         "soax_adjoint": [vp, vp, i64, vp, dbl, i64, i64, vp, vp, vp],
+        "soax_adjoint_noalloc": [vp, vp, i64, vp, dbl, i64, i64, vp, vp, vp],
         "soax_sqdist_loss": [vp, vp, i64, vp, vp, vp],
         "soax_batch_create": [vp, i32, vp],
         "soax_batch_destroy": [vp],

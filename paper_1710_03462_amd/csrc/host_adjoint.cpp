@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -120,6 +121,86 @@ soax_status soax_adjoint(const double* tape, const double* const* lamT, int64_t 
                          const double* abc, double dt, int64_t nsteps, int64_t k,
                          double* const* grad_x0, double* grad_abc, void* stream) {
   return soax_adjoint_strided(tape, lamT, n, 1, abc, dt, nsteps, k, grad_x0, grad_abc, stream);
+}
+
+// ------------------------------------------- allocation-free adjoint
+
+// Device memory of soax_adjoint_noalloc: the adjoint kernel's per-workgroup
+// partial sums of dL/d(A,B,C), three doubles per workgroup of 256 particles,
+// in a fixed array that every GPU the library runs on holds until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on
+// the host the name stands for a host-side symbol, not a device address):
+// it passes the address hipGetSymbolAddress returns for the current device.
+constexpr int64_t kNoAllocScratchBytes = int64_t(1) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];  // per device, set once
+
+// Device address of `scratch` on the current device, looked up on the first
+// call on that device.
+static soax_status scratch_ptr(double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(SOAX_E_STATE, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                               "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<double*>(g_scratch_ptr[dev]);
+  return SOAX_OK;
+}
+
+// Particles whose partial sums fit the scratch: one triple per workgroup.
+static_assert(SOAX_ADJOINT_NOALLOC_MAX_N ==
+                  kNoAllocScratchBytes / (3 * int64_t(sizeof(double))) * kAdjointBlock,
+              "the header's limit must match the scratch size");
+
+soax_status soax_adjoint_noalloc(const double* tape, const double* const* lamT, int64_t n,
+                                 const double* abc, double dt, int64_t nsteps, int64_t k,
+                                 double* const* grad_x0, double* grad_abc, void* stream) {
+  soax_status st;
+  if ((st = check_rows(reinterpret_cast<const void* const*>(lamT), n, "lamT")) ||
+      (st = check_rows(reinterpret_cast<const void* const*>(grad_x0), n, "grad_x0")) ||
+      (st = check_abc_host(abc)))
+    return st;
+  if (!grad_abc) return fail(SOAX_E_ARG, "grad_abc is NULL");
+  if (n < 0) return fail(SOAX_E_ARG, "bad n");
+  const int64_t max_n = SOAX_ADJOINT_NOALLOC_MAX_N;
+  if (n > max_n || adjoint_partials(n) * 3 * int64_t(sizeof(double)) > kNoAllocScratchBytes)
+    return fail(SOAX_E_RANGE,
+                "soax_adjoint_noalloc: n = %lld exceeds its fixed scratch (%lld bytes, at most "
+                "%lld particles); use soax_adjoint",
+                static_cast<long long>(n), static_cast<long long>(kNoAllocScratchBytes),
+                static_cast<long long>(max_n));
+  if (nsteps < 0 || k < 1) return fail(SOAX_E_ARG, "need nsteps >= 0 and k >= 1");
+  if (!is_finite(dt)) return fail(SOAX_E_ARG, "dt is not finite");
+  if (!tape && n > 0 && nsteps > 0) return fail(SOAX_E_ARG, "tape is NULL");
+  double* partial = nullptr;
+  if ((st = scratch_ptr(&partial))) return st;
+  AdjointArgs a{};
+  a.tape = tape;
+  for (int d = 0; d < 3; ++d) {
+    a.lam[d] = lamT[d];
+    a.gx[d] = grad_x0[d];
+  }
+  // every partial the final sum reads is written by the adjoint kernel's
+  // workgroups before it, so nothing needs clearing
+  a.partial = partial;
+  a.grad_abc = grad_abc;
+  a.stride = 1;
+  a.n = n;
+  a.nsteps = nsteps;
+  a.k = k;
+  a.dt = dt;
+  a.abc = AbcParams{abc[0], abc[1], abc[2]};
+  HIP_TRY(launch_adjoint(a, as_stream(stream)), "adjoint launch");
+  return SOAX_OK;
 }
 
 static soax_status sqdist_impl(const double* const* xT, int64_t stride,

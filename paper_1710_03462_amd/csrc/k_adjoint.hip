@@ -21,7 +21,7 @@ namespace soax {
 
 namespace {
 
-constexpr int kRedBlock = 256;  // workgroup size of every reducing kernel
+constexpr int kRedBlock = kAdjointBlock;  // workgroup size of every reducing kernel
 
 
 

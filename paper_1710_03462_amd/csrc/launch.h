@@ -190,6 +190,10 @@ struct CkptArgs {
 };
 hipError_t launch_rk2_forward_ckpt(const CkptArgs& a, hipStream_t s);
 
+// Workgroup size of the adjoint and loss kernels: one partial sum of the
+// parameter gradient per kAdjointBlock particles.
+constexpr int kAdjointBlock = 256;
+
 struct AdjointArgs {
   const double* tape;
   const double* lam[3];

@@ -41,7 +41,8 @@ def test_header_declarations_match_binding_signatures():
              "soax_remove_flagged", "soax_eval", "soax_eval_ptrs", "soax_expr_source",
              "soax_rk2_forward_ckpt_strided", "soax_adjoint_strided", "soax_sqdist_loss_strided",
              "soax_aosoa_layout", "soax_bind_aosoa", "soax_soa_to_aosoa", "soax_aosoa_to_soa",
-             "soax_step_graph_create", "soax_step_graph_launch", "soax_step_graph_destroy"}
+             "soax_step_graph_create", "soax_step_graph_launch", "soax_step_graph_destroy",
+             "soax_adjoint_noalloc"}
     assert declared == bound
 
 
@@ -176,6 +177,14 @@ def test_adjoint_and_loss_validation(L):
     assert a(tape, rows, 10, abc, math.nan, 20, 5, rows, tape, None) == E_ARG
     assert a(tape, none3, 10, abc, 5e-3, 20, 5, rows, tape, None) == E_ARG
     assert L.soax_sqdist_loss(rows, rows, 10, None, None, None) == E_ARG
+    # the allocation-free adjoint: its argument checks and its size limit are
+    # decided on the host, before any device call
+    z = L.soax_adjoint_noalloc
+    assert z(tape, rows, 10, abc, 5e-3, 20, 5, rows, None, None) == E_ARG
+    assert z(tape, rows, 10, abc, 5e-3, 20, 0, rows, tape, None) == E_ARG
+    assert z(tape, rows, -1, abc, 5e-3, 20, 5, rows, tape, None) == E_ARG
+    assert z(tape, rows, 11184640 + 1, abc, 5e-3, 20, 5, rows, tape, None) == E_RANGE
+    assert b"scratch" in L.soax_last_error()
 
 
 def test_copy_and_batch_validation(L):
