@@ -203,6 +203,81 @@ def bench_copy(torch, soax, nbytes=4 << 30):
     return out
 
 
+def bench_probes(torch, soax, n, reps=20):
+    """The memory patterns of the streaming SoA steps with no arithmetic
+    (soax_probe), on arrays allocated like a ParticleSet's (one tensor per
+    array): the ceiling each step kernel is measured against.  rk2 and euler
+    move 60 B per particle, read 24 B, write 36 B."""
+    pos = [torch.rand(n, dtype=torch.float64, device="cuda") * 6.0 for _ in range(3)]
+    vel = [torch.randn(n, dtype=torch.float32, device="cuda") for _ in range(3)]
+    out = {"n": n}
+    for pat, nbytes in (("rk2", 60), ("euler", 60), ("read", 24), ("write", 36)):
+        for _ in range(2):
+            soax.probe(pat, pos, vel)
+        with Timer(torch) as t:
+            for _ in range(reps):
+                soax.probe(pat, pos, vel)
+        per = t.ms / reps
+        out[pat] = {"bytes_per_particle": nbytes, "ms_per_launch": per,
+                    "GBps": gbs(nbytes * n, per), "frac_of_peak": gbs(nbytes * n, per) / HBM_PEAK_GBS}
+    del pos, vel
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_expr_euler(torch, soax, si, ns=(100_000, 100_000_000), nsteps=20, dt=1e-3):
+    """The library's generated form of the Euler update against the
+    hand-written SoA step, call overhead included (the comparison of
+    Section 4.2.2): per step, pos_d = pos_d + dt * vel_d as three fused
+    expression launches, or one soax_step launch (no wrap: the expressions
+    have none).  Kernel time from events, wall time around the calls."""
+    out = {}
+    for n in ns:
+        ps = soax.ParticleSet(si.BASE_FIELDS, n, aos=False)
+        ps.fill(seed=0)
+        progs = [ps.arr("pos", d) + dt * ps.arr("vel", d) for d in range(3)]
+
+        def generated():
+            for d in range(3):
+                ps.assign(("pos", d), progs[d])
+
+        def hand_written():
+            ps.step("soa", "euler", dt, 1, wrap=False)
+
+        row = {"nsteps": nsteps}
+        for name, fn in (("generated", generated), ("hand_written", hand_written)):
+            for _ in range(3):
+                fn()
+            with Timer(torch) as t:
+                w0 = time.perf_counter()
+                for _ in range(nsteps):
+                    fn()
+                torch.cuda.synchronize()
+                w1 = time.perf_counter()
+            row[name] = {"kernel_ms_per_step": t.ms / nsteps,
+                         "wall_ms_per_step": (w1 - w0) * 1e3 / nsteps,
+                         "alg_GBps": gbs(60 * n, t.ms / nsteps)}
+        row["generated_over_hand_written_wall"] = (row["generated"]["wall_ms_per_step"] /
+                                                   row["hand_written"]["wall_ms_per_step"])
+        row["generated_over_hand_written_kernel"] = (row["generated"]["kernel_ms_per_step"] /
+                                                     row["hand_written"]["kernel_ms_per_step"])
+        out[f"n={n:.0e}"] = row
+        ps.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def bench_wide(torch, soax, si, n):
     ps = soax.ParticleSet(si.WIDE_FIELDS, n)
     ps.fill(seed=0)
@@ -458,6 +533,7 @@ def cpu_baseline(ref, si, target_s=20.0):
     ref.step_soa(sch, arrays, ref.RK2_ABC, 1e-3, 50, abc=[1, 1, 1], wrap=True)
     el = time.perf_counter() - t0
     return {"value": n * 50 / el, "unit": "particle-updates/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{n} particles x 50 RK2 steps of the same record and field "
                       f"(SoA, OpenMP static schedule), {el:.1f} s"}
 
@@ -483,8 +559,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=float, default=1e8, help="particles of the headline workload")
     ap.add_argument("--rows", default="all",
-                    help="comma list of extra rows: aos,euler,small,copy,wide,adjoint,batch,"
-                         "remove,expr,integrators,aosoa | all | none")
+                    help="comma list of extra rows: aos,euler,small,copy,probes,wide,adjoint,"
+                         "batch,remove,expr,expr_euler,integrators,aosoa | all | none")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--sweep", action="store_true",
                     help="run only the N x SIZE sweep of the paper's GPU experiment and print "
@@ -511,8 +587,8 @@ def main():
         print(json.dumps({"sweep": bench_sweep(torch, soax, si, sizes, ns),
                           "device": torch.cuda.get_device_name(0)}), flush=True)
         return 0
-    rows = {"aos", "euler", "small", "copy", "wide", "adjoint", "batch", "remove", "expr",
-            "integrators", "aosoa"} \
+    rows = {"aos", "euler", "small", "copy", "probes", "wide", "adjoint", "batch", "remove",
+            "expr", "expr_euler", "integrators", "aosoa"} \
         if args.rows == "all" else \
         set() if args.rows == "none" else set(args.rows.split(","))
     n = int(args.n)
@@ -569,6 +645,16 @@ def main():
     if "copy" in rows:
         log("[bench] copy ceiling")
         out_rows["copy"] = bench_copy(torch, soax)
+    if "probes" in rows:
+        log("[bench] stream probes: the step patterns without arithmetic")
+        out_rows["probes"] = bench_probes(torch, soax, n)
+        probe = out_rows["probes"]["rk2"]["GBps"]
+        roofline["pattern_ceiling"] = {"probe": "soax_probe rk2 (same loads and stores, no "
+                                                "arithmetic)", "GBps": probe,
+                                       "frac_of_probe": roofline["achieved"] / probe}
+        if "euler_soa" in out_rows:
+            out_rows["euler_soa"]["frac_of_probe"] = (out_rows["euler_soa"]["physical_GBps"] /
+                                                      out_rows["probes"]["euler"]["GBps"])
     if "wide" in rows:
         log("[bench] wide record: transposes and Euler with acceleration")
         out_rows["wide"] = bench_wide(torch, soax, si, 30_000_000)
@@ -584,6 +670,9 @@ def main():
     if "expr" in rows:
         log("[bench] fused array expressions")
         out_rows["expr"] = bench_expr(torch, soax, si, n)
+    if "expr_euler" in rows:
+        log("[bench] generated Euler update vs the hand-written step")
+        out_rows["expr_euler"] = bench_expr_euler(torch, soax, si)
     torch.cuda.empty_cache()
 
     cpu = None

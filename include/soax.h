@@ -481,6 +481,27 @@ soax_status soax_batch_tune(soax_batch* batch, const char* cache_path);
  * pointers): the bandwidth probe the step kernels are measured against. */
 soax_status soax_copy(void* dst, const void* src, int64_t bytes, void* stream);
 
+/*
+ * Bandwidth probes: the memory accesses of the streaming SoA steps with their
+ * arithmetic taken out, on caller-owned device arrays pos[3] (n doubles each)
+ * and vel[3] (n floats each), one particle per thread with the step kernels'
+ * loads, stores and cache hints.  They bound what the step kernels can reach
+ * on this memory system, as soax_copy bounds plain streaming:
+ *   SOAX_PROBE_RK2    read pos, write pos (unchanged) and vel = (float)pos:
+ *                     the 60 B per particle of an RK2, Heun or RK4 step;
+ *   SOAX_PROBE_EULER  per component read pos and vel, write pos (unchanged
+ *                     for finite vel): the 60 B of an Euler step;
+ *   SOAX_PROBE_READ   read pos only (24 B; writes nothing, vel may be NULL);
+ *   SOAX_PROBE_WRITE  write pos = 0 and vel = 0 (36 B; destroys the values).
+ * Errors: ARG (bad pattern, NULL array, n < 0), RANGE (n > 2^31-1), HIP.
+ */
+#define SOAX_PROBE_RK2 0
+#define SOAX_PROBE_EULER 1
+#define SOAX_PROBE_READ 2
+#define SOAX_PROBE_WRITE 3
+soax_status soax_probe(int32_t pattern, double* const* pos, float* const* vel, int64_t n,
+                       void* stream);
+
 const char* soax_strerror(soax_status status);
 const char* soax_last_error(void);
 

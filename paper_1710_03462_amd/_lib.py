@@ -110,6 +110,7 @@ def lib():
         "soax_step_graph_launch": [vp, vp],
         "soax_step_graph_destroy": [vp],
         "soax_copy": [vp, vp, i64, vp],
+        "soax_probe": [i32, vp, vp, i64, vp],
         "soax_strerror": [i32],
         "soax_last_error": [],
     }

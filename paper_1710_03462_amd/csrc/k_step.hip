@@ -695,6 +695,45 @@ __global__ void copy_tail_kernel(char* dst, const char* src, int64_t from, int64
   if (i < bytes) dst[i] = src[i];
 }
 
+// ------------------------------------------------------------ stream probes
+
+// The memory accesses of the streaming SoA step kernels with their
+// arithmetic taken out: one particle per thread, positions loaded with
+// ordinary loads, every store and every read-only load nontemporal, as in
+// soa_step_kernel<..., STREAM = true>.  a.c is 0 for the patterns that
+// write (positions are rewritten unchanged) and NaN for the read-only one,
+// whose single guarded store never fires but keeps the loads alive.
+template <int PAT>
+__global__ __launch_bounds__(1024) void stream_probe_kernel(ProbeArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  if constexpr (PAT == kProbeRk2) {
+    const double x = a.pos[0][i], y = a.pos[1][i], z = a.pos[2][i];
+    st1<true>(a.pos[0] + i, x + a.c);
+    st1<true>(a.pos[1] + i, y + a.c);
+    st1<true>(a.pos[2] + i, z + a.c);
+    st1<true>(a.vel[0] + i, static_cast<float>(x));
+    st1<true>(a.vel[1] + i, static_cast<float>(y));
+    st1<true>(a.vel[2] + i, static_cast<float>(z));
+  } else if constexpr (PAT == kProbeEuler) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double x = a.pos[d][i];
+      const float v = ld1<true>(a.vel[d] + i);
+      st1<true>(a.pos[d] + i, x + a.c * static_cast<double>(v));
+    }
+  } else if constexpr (PAT == kProbeRead) {
+    const double s = (a.pos[0][i] + a.pos[1][i]) + a.pos[2][i];
+    if (s == a.c) a.pos[0][i] = s;
+  } else {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      st1<true>(a.pos[d] + i, a.c);
+      st1<true>(a.vel[d] + i, static_cast<float>(a.c));
+    }
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -871,6 +910,27 @@ hipError_t launch_copy16(void* dst, const void* src, int64_t bytes, hipStream_t 
   if (bytes & 15) {
     hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(16), 0, s, static_cast<char*>(dst),
                        static_cast<const char*>(src), n16 << 4, bytes);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_probe(int pattern, const ProbeArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const int block = 128;  // the SoA step's default workgroup
+  const int64_t grid = (a.n + block - 1) / block;
+  switch (pattern) {
+    case kProbeRk2:
+      hipLaunchKernelGGL(stream_probe_kernel<kProbeRk2>, dim3(grid), dim3(block), 0, s, a);
+      break;
+    case kProbeEuler:
+      hipLaunchKernelGGL(stream_probe_kernel<kProbeEuler>, dim3(grid), dim3(block), 0, s, a);
+      break;
+    case kProbeRead:
+      hipLaunchKernelGGL(stream_probe_kernel<kProbeRead>, dim3(grid), dim3(block), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL(stream_probe_kernel<kProbeWrite>, dim3(grid), dim3(block), 0, s, a);
+      break;
   }
   return hipGetLastError();
 }

@@ -172,6 +172,17 @@ hipError_t launch_vel_from_field(int pos_t, int vel_t, const SoaStepArgs& a, hip
 
 hipError_t launch_copy16(void* dst, const void* src, int64_t bytes, hipStream_t s);
 
+// Access patterns of the streaming SoA steps without their arithmetic (the
+// values of the soax_probe patterns).
+enum ProbePattern : int32_t { kProbeRk2 = 0, kProbeEuler = 1, kProbeRead = 2, kProbeWrite = 3 };
+struct ProbeArgs {
+  double* pos[3];
+  float* vel[3];
+  int64_t n;
+  double c;
+};
+hipError_t launch_stream_probe(int pattern, const ProbeArgs& a, hipStream_t s);
+
 // --------------------------------------------------------------- adjoint
 
 // Position-like arrays (x0, xT, lam, gx) are read at element i * stride:

@@ -461,6 +461,25 @@ extern "C" soax_status soax_copy(void* dst, const void* src, int64_t bytes, void
   return SOAX_OK;
 }
 
+extern "C" soax_status soax_probe(int32_t pattern, double* const* pos, float* const* vel,
+                                  int64_t n, void* stream) {
+  if (pattern < kProbeRk2 || pattern > kProbeWrite) return fail(SOAX_E_ARG, "unknown probe pattern %d", pattern);
+  if (n < 0 || n > kMaxParticles) return fail(n < 0 ? SOAX_E_ARG : SOAX_E_RANGE, "bad n");
+  if (n == 0) return SOAX_OK;
+  if (!pos || !pos[0] || !pos[1] || !pos[2]) return fail(SOAX_E_ARG, "pos is NULL");
+  const bool writes_vel = pattern == kProbeRk2 || pattern == kProbeEuler || pattern == kProbeWrite;
+  if (writes_vel && (!vel || !vel[0] || !vel[1] || !vel[2])) return fail(SOAX_E_ARG, "vel is NULL");
+  ProbeArgs a{};
+  for (int d = 0; d < 3; ++d) {
+    a.pos[d] = pos[d];
+    a.vel[d] = writes_vel ? vel[d] : nullptr;
+  }
+  a.n = n;
+  a.c = pattern == kProbeRead ? __builtin_nan("") : 0.0;
+  HIP_TRY(launch_stream_probe(pattern, a, as_stream(stream)), "probe launch");
+  return SOAX_OK;
+}
+
 extern "C" const char* soax_strerror(soax_status st) {
   switch (st) {
     case SOAX_OK: return "ok";

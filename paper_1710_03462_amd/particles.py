@@ -337,3 +337,22 @@ def copy(dst, src):
     assert dst.numel() * dst.element_size() >= nbytes
     check(lib().soax_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
                           nbytes, current_stream()), "soax_copy")
+
+
+PROBES = {"rk2": 0, "euler": 1, "read": 2, "write": 3}
+
+
+def probe(pattern, pos, vel=None):
+    """One launch of a bandwidth probe (soax_probe) on three float64 position
+    tensors and three float32 velocity tensors of n elements each: "rk2",
+    "euler", "read" or "write"."""
+    n = pos[0].numel()
+    for t in pos:
+        assert t.dtype == torch.float64 and t.numel() == n
+    pp = (ctypes.c_void_p * 3)(*[t.data_ptr() for t in pos])
+    vp = None
+    if vel is not None:
+        for t in vel:
+            assert t.dtype == torch.float32 and t.numel() == n
+        vp = (ctypes.c_void_p * 3)(*[t.data_ptr() for t in vel])
+    check(lib().soax_probe(PROBES[pattern], pp, vp, n, current_stream()), "soax_probe")

@@ -42,7 +42,7 @@ def test_header_declarations_match_binding_signatures():
              "soax_rk2_forward_ckpt_strided", "soax_adjoint_strided", "soax_sqdist_loss_strided",
              "soax_aosoa_layout", "soax_bind_aosoa", "soax_soa_to_aosoa", "soax_aosoa_to_soa",
              "soax_step_graph_create", "soax_step_graph_launch", "soax_step_graph_destroy",
-             "soax_adjoint_noalloc"}
+             "soax_adjoint_noalloc", "soax_probe"}
     assert declared == bound
 
 
@@ -191,6 +191,14 @@ def test_copy_and_batch_validation(L):
     assert L.soax_copy(ctypes.c_void_p(0x1008), ctypes.c_void_p(0x2000), 64, None) == E_ARG
     assert L.soax_copy(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), -1, None) == E_ARG
     assert L.soax_copy(None, None, 0, None) == 0
+    rows = (ctypes.c_void_p * 3)(0x1000, 0x2000, 0x3000)
+    none3 = (ctypes.c_void_p * 3)(0x1000, None, 0x3000)
+    assert L.soax_probe(4, rows, rows, 10, None) == E_ARG
+    assert L.soax_probe(0, rows, none3, 10, None) == E_ARG
+    assert L.soax_probe(0, none3, rows, 10, None) == E_ARG
+    assert L.soax_probe(1, rows, rows, -1, None) == E_ARG
+    assert L.soax_probe(0, rows, rows, 2 ** 31, None) == E_RANGE
+    assert L.soax_probe(2, None, None, 0, None) == 0
     h = ctypes.c_void_p()
     assert L.soax_batch_create(None, 0, ctypes.byref(h)) == E_ARG
     arr = (ctypes.c_void_p * 1)(None)

@@ -137,3 +137,32 @@ def test_empty_and_errors():
     with pytest.raises(soax.SoaxError):
         ps.assign(("id", 0), ps.arr("vel", 0) * 2.0)  # integer destination
     ps.close()
+
+
+@pytest.mark.parametrize("n", [257, 100_003, 4_000_003])
+def test_generated_euler_update_equals_the_step_kernel(n):
+    """The Euler update written as three generated expressions,
+    pos_d = pos_d + dt * vel_d (Section 4.2.2 compares this form with the
+    hand-written SoA loop), gives the step kernel's results bit for bit: both
+    are one double multiply and one double add per component; the oracle's
+    Euler step without wrap agrees too."""
+    fields, dt, steps = si.BASE_FIELDS, 1e-3, 7
+    arrays = si.random_state(fields, n, seed=n + 3)
+    gen = soax.ParticleSet(fields, n, aos=False)
+    hand = soax.ParticleSet(fields, n, aos=False)
+    gen.upload_soa(arrays)
+    hand.upload_soa(arrays)
+    progs = [gen.arr("pos", d) + dt * gen.arr("vel", d) for d in range(3)]
+    for _ in range(steps):
+        for d in range(3):
+            gen.assign(("pos", d), progs[d])
+    hand.step("soa", "euler", dt, steps, wrap=False)
+    torch.cuda.synchronize()
+    got, want_gpu = gen.download_soa(), hand.download_soa()
+    want = [a.copy() for a in arrays]
+    ref.step_soa(ref.Schema(fields), want, ref.EULER, dt, steps, wrap=False)
+    for a in range(len(arrays)):
+        assert np.array_equal(got[a], want_gpu[a]), a
+        assert np.array_equal(got[a], want[a]), a
+    gen.close()
+    hand.close()
