@@ -368,9 +368,15 @@ soax_status soax_expr_source(const soax_expr_op* prog, int32_t nops, int32_t dst
 /*
  * RK2 (explicit midpoint) advection of n positions in the ABC field with
  * amplitudes abc[3] (host), no wrap: x0[d], xT[d] are device arrays of n
- * doubles (d = 0, 1, 2; xT may alias x0).  The state before steps
- * 0, k, 2k, ... < nsteps is written to tape[c][d][i] (device,
- * ceil(nsteps/k) * 3 * n doubles), the checkpoints of the adjoint.
+ * doubles (d = 0, 1, 2; xT may alias x0).  The checkpoints of the adjoint,
+ * the states before steps 0, k, 2k, ... < nsteps, are written to
+ * tape[c][r][i] (device, ceil(nsteps/k) * 9 * n doubles): rows r = 0..2 the
+ * position, rows 3..8 sin x, cos x, sin y, cos y, sin z, cos z as the
+ * forward evaluated them.  When |dt| (|A| + |B| + |C|) <= 1/64 every step's
+ * sines and cosines come from the previous step's by angle addition, with a
+ * full evaluation every 16 steps; the results depend on the step index only,
+ * never on k.  Errors: ARG (NULL array or tape, n < 0, nsteps < 0, k < 1,
+ * non-finite dt or amplitude), RANGE (n > 2^31-1), HIP.
  */
 soax_status soax_rk2_forward_ckpt(const double* const* x0, double* const* xT, int64_t n,
                                   const double* abc, double dt, int64_t nsteps, int64_t k,
@@ -418,7 +424,7 @@ soax_status soax_sqdist_loss(const double* const* xT, const double* const* targe
  * stride 1 is the SoA form above; the record stride / 8 with pointers to a
  * record's pos[d] keeps the positions inside AoS records (the AoS side of
  * the SoA/AoS comparison for the adjoint).  target stays SoA; the tape is
- * always [segment][3][n].  Results are bit-identical to the SoA form. */
+ * always [segment][9][n].  Results are bit-identical to the SoA form. */
 soax_status soax_rk2_forward_ckpt_strided(const double* const* x0, double* const* xT, int64_t n,
                                           int64_t stride, const double* abc, double dt,
                                           int64_t nsteps, int64_t k, double* tape, void* stream);

@@ -15,6 +15,11 @@ from ._lib import check, lib
 from .particles import current_stream
 
 
+# Rows of one checkpoint on the tape: the position and the sines and cosines
+# of its three coordinates.
+TAPE_ROWS = 9
+
+
 def _rows(t):
     """Row pointers of a contiguous [3, n] float64 tensor."""
     assert t.dtype == torch.float64 and t.is_contiguous() and t.shape[0] == 3
@@ -31,7 +36,7 @@ def forward_ckpt(pos0, abc_host, dt, nsteps, k):
     n = pos0.shape[1]
     xT = torch.empty_like(pos0)
     nck = max(1, -(-int(nsteps) // int(k)))
-    tape = torch.empty((nck, 3, max(n, 1)), dtype=torch.float64, device=pos0.device)
+    tape = torch.empty((nck, TAPE_ROWS, max(n, 1)), dtype=torch.float64, device=pos0.device)
     check(lib().soax_rk2_forward_ckpt(_rows(pos0), _rows(xT), n, abc_host, float(dt), int(nsteps),
                                       int(k), ctypes.c_void_p(tape.data_ptr()), current_stream()),
           "soax_rk2_forward_ckpt")
@@ -78,7 +83,8 @@ def forward_ckpt_records(x0_rec, xT_rec, pos_offset, stride, n, abc_host, dt, ns
     r0, sd = _record_rows(x0_rec, pos_offset, stride)
     rT, _ = _record_rows(xT_rec, pos_offset, stride)
     nck = max(1, -(-int(nsteps) // int(k)))
-    tape = torch.empty((nck, 3, max(n, 1)), dtype=torch.float64, device=x0_rec.device)
+    tape = torch.empty((nck, TAPE_ROWS, max(n, 1)), dtype=torch.float64,
+                       device=x0_rec.device)
     check(lib().soax_rk2_forward_ckpt_strided(r0, rT, n, sd, abc_host, float(dt), int(nsteps),
                                               int(k), ctypes.c_void_p(tape.data_ptr()),
                                               current_stream()), "soax_rk2_forward_ckpt_strided")

@@ -102,22 +102,6 @@ __device__ __forceinline__ Abc scaled(const Abc& p, double s) {
   return Abc{s * p.A, s * p.B, s * p.C};
 }
 
-// One explicit-midpoint step without wrap, for loops over many steps of one
-// particle: (dt/2) k1 and dt k2 are the fields of the amplitudes scaled by
-// dt/2 and dt, which a loop computes once instead of scaling each stage.
-template <bool SMALL>
-__device__ __forceinline__ void rk2_midpoint(const Abc& p, double dt, double& x, double& y,
-                                             double& z) {
-  const Trig3 t = trig3(x, y, z);
-  double m0, m1, m2;
-  field_of(scaled(p, 0.5 * dt), t, m0, m1, m2);
-  const Trig3 tm = trig3_shift<SMALL>(t, x, y, z, m0, m1, m2);
-  field_of(scaled(p, dt), tm, m0, m1, m2);
-  x = x + m0;
-  y = y + m1;
-  z = z + m2;
-}
-
 // Alignment (bytes) of a run of VEC consecutive T starting at a multiple of
 // VEC elements in a 16-byte aligned array.
 template <typename T, int VEC>

@@ -25,6 +25,41 @@ constexpr int kRedBlock = kAdjointBlock;  // workgroup size of every reducing ke
 
 
 
+// Rows of one checkpoint on the tape: the position and the sines and cosines
+// the forward evaluated at it.
+constexpr int kTapeRows = 9;
+
+// Sines and cosines of the state of step s (its global index) in the loops
+// over many steps of one particle.  With every step proven small (SMALL)
+// they come from the previous state's by angle addition over the step's
+// displacement (the difference of the two rounded positions), renewed by a
+// full reduction at every step index that is a multiple of kAnchor, so each
+// value depends on the step index alone (not on the checkpoint interval) and
+// carries at most kAnchor - 1 angle additions (about one ulp of 1 each).
+// Larger steps reduce every state in full.
+constexpr int64_t kAnchor = 16;
+
+// One explicit-midpoint step from (x, y, z) with sines and cosines t, no
+// wrap; on return (x, y, z) is the state of step s + 1 and t its sines and
+// cosines as above.  (dt/2) k1 and dt k2 are the fields of the amplitudes
+// scaled by dt/2 and dt, which a loop computes once.
+template <bool SMALL>
+__device__ __forceinline__ void rk2_advance(const Abc& p, double dt, int64_t s, double& x,
+                                            double& y, double& z, Trig3& t) {
+  double m0, m1, m2;
+  field_of(scaled(p, 0.5 * dt), t, m0, m1, m2);
+  const Trig3 tm = trig3_shift<SMALL>(t, x, y, z, m0, m1, m2);
+  field_of(scaled(p, dt), tm, m0, m1, m2);
+  const double x1 = x + m0, y1 = y + m1, z1 = z + m2;
+  if (!SMALL || (s + 1) % kAnchor == 0)
+    t = trig3(x1, y1, z1);
+  else
+    t = trig3_shift<SMALL>(t, x, y, z, x1 - x, y1 - y, z1 - z);
+  x = x1;
+  y = y1;
+  z = z1;
+}
+
 template <bool SMALL>
 __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -32,6 +67,7 @@ __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
   const Abc p = to_abc(a.abc);
   const int64_t e = i * a.stride;
   double x = a.x0[0][e], y = a.x0[1][e], z = a.x0[2][e];
+  Trig3 t = trig3(x, y, z);
   double* tp = a.tape + i;
   const int64_t n = a.n;
   int64_t until_ckpt = 0;
@@ -40,28 +76,33 @@ __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
       st1<true>(tp, x);
       st1<true>(tp + n, y);
       st1<true>(tp + 2 * n, z);
-      tp += 3 * n;
+      st1<true>(tp + 3 * n, t.sx);
+      st1<true>(tp + 4 * n, t.cx);
+      st1<true>(tp + 5 * n, t.sy);
+      st1<true>(tp + 6 * n, t.cy);
+      st1<true>(tp + 7 * n, t.sz);
+      st1<true>(tp + 8 * n, t.cz);
+      tp += kTapeRows * n;
       until_ckpt = a.k;
     }
     --until_ckpt;
-    rk2_midpoint<SMALL>(p, a.dt, x, y, z);
+    rk2_advance<SMALL>(p, a.dt, s, x, y, z, t);
   }
   st1<true>(a.xT[0] + e, x);
   st1<true>(a.xT[1] + e, y);
   st1<true>(a.xT[2] + e, z);
 }
 
-// Reverse one midpoint step taken from state (x, y, z).  With
-// xm = x + (dt/2) u(x) and x+ = x + dt u(xm):
+// Reverse one midpoint step taken from state (x, y, z), whose sines and
+// cosines are t.  With xm = x + (dt/2) u(x) and x+ = x + dt u(xm):
 //   mu  = dt J(xm)^T lam+
 //   g  += dt G(xm)^T lam+ + (dt/2) G(x)^T mu
 //   lam = lam+ + mu + (dt/2) J(x)^T mu
 // where J = du/dx and G = du/d(A,B,C).
 template <bool SMALL>
-__device__ __forceinline__ void rk2_reverse(const Abc& p, double dt, double x, double y, double z,
-                                            double& l0, double& l1, double& l2, double& g0,
-                                            double& g1, double& g2) {
-  const Trig3 t = trig3(x, y, z);
+__device__ __forceinline__ void rk2_reverse(const Abc& p, double dt, const Trig3& t, double x,
+                                            double y, double z, double& l0, double& l1,
+                                            double& l2, double& g0, double& g1, double& g2) {
   const double h = 0.5 * dt;
   double h0, h1, h2;  // (dt/2) u(x), as in the forward step
   field_of(scaled(p, h), t, h0, h1, h2);
@@ -86,6 +127,13 @@ __device__ __forceinline__ void rk2_reverse(const Abc& p, double dt, double x, d
   l1 = (l1 + m1) + hC * fma(t.cy, m2, -(t.sy * m0));
   l2 = (l2 + m2) + hA * fma(t.cz, m0, -(t.sz * m1));
 }
+
+// With every step proven small (SMALL), the reverse sweep takes the sines
+// and cosines of each state from those of the state one step later (reversed
+// just before it) by angle addition over the difference of the two
+// positions, renewed by a full reduction at the last step and at every step
+// whose index is kAnchor - 1 modulo kAnchor; like the forward's, these values
+// depend on the step index alone.  Larger steps reduce every state in full.
 
 // Sum v over the workgroup (kRedBlock threads) in a fixed tree order.
 __device__ __forceinline__ void block_sum3(double v0, double v1, double v2, double* out3) {
@@ -122,13 +170,17 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
     const int64_t e = i * a.stride;
     double l0 = a.lam[0][e], l1 = a.lam[1][e], l2 = a.lam[2][e];
     const int64_t nseg = (a.nsteps + a.k - 1) / a.k;
+    Trig3 tn{};  // sines and cosines of the state reversed last, at (xn, yn, zn)
+    double xn = 0.0, yn = 0.0, zn = 0.0;
     for (int64_t c = nseg - 1; c >= 0; --c) {
       const int64_t len = min(a.k, a.nsteps - c * a.k);
-      const double* cp = a.tape + (c * 3) * n + i;
+      const double* cp = a.tape + (c * kTapeRows) * n + i;
       const int64_t nsub = (len + KM - 1) / KM;
       for (int64_t q = nsub - 1; q >= 0; --q) {
         double x = cp[0], y = cp[n], z = cp[2 * n];
-        for (int64_t s = 0; s < q * KM; ++s) rk2_midpoint<SMALL>(p, dt, x, y, z);
+        Trig3 t{cp[3 * n], cp[4 * n], cp[5 * n], cp[6 * n], cp[7 * n], cp[8 * n]};
+        int64_t s = c * a.k;  // global index of the state (x, y, z)
+        for (; s < c * a.k + q * KM; ++s) rk2_advance<SMALL>(p, dt, s, x, y, z, t);
         const int m = static_cast<int>(min(static_cast<int64_t>(KM), len - q * KM));
         double sx[KM], sy[KM], sz[KM];
 #pragma unroll
@@ -137,12 +189,25 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
             sx[j] = x;
             sy[j] = y;
             sz[j] = z;
-            if (j + 1 < m) rk2_midpoint<SMALL>(p, dt, x, y, z);
+            if (j + 1 < m) rk2_advance<SMALL>(p, dt, s + j, x, y, z, t);
           }
         }
+        const int64_t t0 = c * a.k + q * KM;  // global index of state 0
 #pragma unroll
         for (int j = KM - 1; j >= 0; --j) {
-          if (j < m) rk2_reverse<SMALL>(p, dt, sx[j], sy[j], sz[j], l0, l1, l2, g0, g1, g2);
+          if (j < m) {
+            const int64_t ts = t0 + j;
+            Trig3 tj;
+            if (!SMALL || ts == a.nsteps - 1 || ts % kAnchor == kAnchor - 1)
+              tj = trig3(sx[j], sy[j], sz[j]);
+            else
+              tj = trig3_shift<SMALL>(tn, xn, yn, zn, sx[j] - xn, sy[j] - yn, sz[j] - zn);
+            rk2_reverse<SMALL>(p, dt, tj, sx[j], sy[j], sz[j], l0, l1, l2, g0, g1, g2);
+            tn = tj;
+            xn = sx[j];
+            yn = sy[j];
+            zn = sz[j];
+          }
         }
       }
     }
