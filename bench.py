@@ -479,13 +479,25 @@ def bench_batch(torch, soax, si, nsets=256, nsteps=100):
     return res
 
 
+SWEEP_LAYOUTS = ("soa", "aos", "aos_naive")
+SWEEP_WARM = 5
+
+
+def sweep_steps(n, steps=None):
+    """Timed steps of one sweep point: 2e8 particle-steps, 20 to 2000 steps."""
+    return steps if steps else max(20, min(2000, int(2e8 // n)))
+
+
 def bench_sweep(torch, soax, si, sizes=(0, 4, 8, 16, 32),
-                ns=(1_000, 10_000, 100_000, 1_000_000, 10_000_000, 100_000_000)):
+                ns=(1_000, 10_000, 100_000, 1_000_000, 10_000_000, 100_000_000), steps=None):
     """The paper's GPU experiment (Section 3.2) on this GPU: the Euler step of
     Listing 4's particle (float x[3], v[3], temp[SIZE]) in SoA, LDS-staged AoS
     and per-thread AoS (the paper's access pattern), time per particle-step
     against the particle count N.  Algorithmic bytes per particle-step: 36
-    (x and v read, x written); the AoS copies move whole records (2 * stride)."""
+    (x and v read, x written); the AoS copies move whole records (2 * stride).
+    Per point and layout: SWEEP_WARM untimed steps, then sweep_steps() timed
+    ones, each one launch; --sweep-report reads the same sequence of launches
+    back from a rocprofv3 trace."""
     rows = []
     for size in sizes:
         fields = si.particle_size_fields(size)
@@ -493,10 +505,10 @@ def bench_sweep(torch, soax, si, sizes=(0, 4, 8, 16, 32),
             ps = soax.ParticleSet(fields, n)
             ps.fill(seed=0)
             ps.soa_to_aos()
-            nsteps = max(20, min(2000, int(2e8 // n)))
+            nsteps = sweep_steps(n, steps)
             row = {"SIZE": size, "N": n, "record_bytes": ps.stride, "nsteps": nsteps}
-            for lay in ("soa", "aos", "aos_naive"):
-                ps.step(lay, "euler", 1e-3, 5, wrap=False)
+            for lay in SWEEP_LAYOUTS:
+                ps.step(lay, "euler", 1e-3, SWEEP_WARM, wrap=False)
                 with Timer(torch) as t:
                     ps.step(lay, "euler", 1e-3, nsteps, wrap=False)
                 per = t.ms / nsteps
@@ -514,6 +526,164 @@ def bench_sweep(torch, soax, si, sizes=(0, 4, 8, 16, 32),
             del ps
             torch.cuda.empty_cache()
     return rows
+
+
+SWEEP_KERNELS = {"soa": re.compile(r"(?<![A-Za-z_])soa_step_kernel<"),
+                 "aos": re.compile(r"(?<![A-Za-z_])aos_step_kernel<"),
+                 "aos_naive": re.compile(r"(?<![A-Za-z_])aos_naive_kernel<")}
+
+
+def _find_csv(path, suffix):
+    if os.path.isfile(path):
+        return path if path.endswith(suffix) else None
+    for dirpath, _, files in os.walk(path):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                return os.path.join(dirpath, f)
+    return None
+
+
+def _col(row, *names):
+    for nm in names:
+        if nm in row and row[nm] != "":
+            return row[nm]
+    raise KeyError(names)
+
+
+def sweep_report(trace_dir, sizes, ns, steps=None):
+    """Per-launch kernel durations (and counters, when the directory holds a
+    counter run) of the sweep, read from rocprofv3 output: the way the paper
+    times its GPU experiment, with each kernel's execution isolated from the
+    host's launch overhead (Section 3.2).  The step launches are matched, in
+    dispatch order, to the sweep's sequence of points and layouts; every
+    matched run must hold SWEEP_WARM + nsteps launches of the layout's kernel.
+    Time per particle-step is the median duration of the timed launches / N."""
+    import csv
+    import statistics
+    plan = [(size, n, lay, sweep_steps(n, steps)) for size in sizes for n in ns
+            for lay in SWEEP_LAYOUTS]
+
+    def runs_of(dispatches):
+        # dispatches: (id, layout, grid, payload) in dispatch order
+        runs = []
+        for d in dispatches:
+            if runs and runs[-1]["layout"] == d[1] and runs[-1]["grid"] == d[2]:
+                runs[-1]["items"].append(d[3])
+            else:
+                runs.append({"layout": d[1], "grid": d[2], "items": [d[3]]})
+        return runs
+
+    def layout_of(name):
+        for lay, rx in SWEEP_KERNELS.items():
+            if rx.search(name):
+                return lay
+        return None
+
+    def check(runs, what):
+        if len(runs) != len(plan):
+            raise SystemExit(f"{what}: {len(runs)} runs of step launches, the sweep has "
+                             f"{len(plan)} points x layouts")
+        for r, (size, n, lay, nst) in zip(runs, plan):
+            if r["layout"] != lay or len(r["items"]) != SWEEP_WARM + nst:
+                raise SystemExit(f"{what}: run {r['layout']} x{len(r['items'])} does not match "
+                                 f"SIZE={size} N={n} {lay} ({SWEEP_WARM}+{nst} launches)")
+
+    out = {}
+    trace = _find_csv(trace_dir, "kernel_trace.csv")
+    if trace:
+        disp = []
+        with open(trace) as f:
+            for row in csv.DictReader(f):
+                lay = layout_of(row["Kernel_Name"])
+                if lay is None:
+                    continue
+                dur = int(_col(row, "End_Timestamp")) - int(_col(row, "Start_Timestamp"))
+                disp.append((int(_col(row, "Dispatch_Id")), lay,
+                             int(_col(row, "Grid_Size_X", "Grid_Size")), dur))
+        disp.sort()
+        runs = runs_of(disp)
+        check(runs, trace)
+        for r, (size, n, lay, nst) in zip(runs, plan):
+            ns_med = statistics.median(r["items"][SWEEP_WARM:])
+            out.setdefault((size, n), {})[lay] = {"kernel_ns": ns_med,
+                                                 "ns_per_particle": ns_med / n,
+                                                 "SoA_alg_GBps": 36 * n / ns_med}
+    cnt = _find_csv(trace_dir, "counter_collection.csv")
+    if cnt:
+        per = {}
+        with open(cnt) as f:
+            for row in csv.DictReader(f):
+                lay = layout_of(row["Kernel_Name"])
+                if lay is None:
+                    continue
+                key = (int(_col(row, "Dispatch_Id")), lay, int(_col(row, "Grid_Size_X", "Grid_Size")))
+                per.setdefault(key, {})
+                nm = row["Counter_Name"]
+                per[key][nm] = per[key].get(nm, 0.0) + float(row["Counter_Value"])
+        disp = sorted((k[0], k[1], k[2], v) for k, v in per.items())
+        runs = runs_of(disp)
+        check(runs, cnt)
+        for r, (size, n, lay, nst) in zip(runs, plan):
+            timed = r["items"][SWEEP_WARM:]
+            names = sorted(timed[0])
+            avg = {nm: sum(t.get(nm, 0.0) for t in timed) / len(timed) for nm in names}
+            out.setdefault((size, n), {}).setdefault(lay, {})["counters_per_launch"] = avg
+    if not out:
+        raise SystemExit(f"no kernel_trace.csv or counter_collection.csv under {trace_dir}")
+    return out
+
+
+def sweep_report_rows(dirs, sizes, ns, steps=None):
+    """sweep_report over several rocprofv3 output directories of the same
+    sweep (a kernel trace and counter runs), merged per point and layout."""
+    out = {}
+    for d in dirs:
+        for key, lays in sweep_report(d, sizes, ns, steps).items():
+            for lay, v in lays.items():
+                tgt = out.setdefault(key, {}).setdefault(lay, {})
+                cnt = v.pop("counters_per_launch", None)
+                tgt.update(v)
+                if cnt:
+                    tgt.setdefault("counters_per_launch", {}).update(cnt)
+    rows = []
+    for (size, n), v in sorted(out.items()):
+        row = {"SIZE": size, "N": n, **v}
+        if all("ns_per_particle" in v.get(lay, {}) for lay in SWEEP_LAYOUTS):
+            row["aos_over_soa"] = v["aos"]["ns_per_particle"] / v["soa"]["ns_per_particle"]
+            row["naive_over_soa"] = v["aos_naive"]["ns_per_particle"] / v["soa"]["ns_per_particle"]
+        rows.append(row)
+    return rows
+
+
+def sweep_markdown(rows):
+    """The merged sweep rows as a markdown table: kernel time per launch,
+    time per particle-step, the AoS/SoA ratios and, where counters were
+    taken, the L2 hit rate TCC_HIT / (TCC_HIT + TCC_MISS) and the vector-L1
+    hit rate 1 - (TCP_TCC_READ_REQ + TCP_TCC_WRITE_REQ) /
+    TCP_TOTAL_CACHE_ACCESSES."""
+    def hits(v):
+        c = v.get("counters_per_launch", {})
+        l2 = l1 = ""
+        if c.get("TCC_HIT_sum", 0) + c.get("TCC_MISS_sum", 0) > 0:
+            l2 = f"{c['TCC_HIT_sum'] / (c['TCC_HIT_sum'] + c['TCC_MISS_sum']):.2f}"
+        if c.get("TCP_TOTAL_CACHE_ACCESSES_sum", 0) > 0:
+            miss = c.get("TCP_TCC_READ_REQ_sum", 0) + c.get("TCP_TCC_WRITE_REQ_sum", 0)
+            l1 = f"{1 - miss / c['TCP_TOTAL_CACHE_ACCESSES_sum']:.2f}"
+        return l1, l2
+
+    lines = ["| SIZE | N | SoA µs | AoS µs | naive µs | SoA ns/p | AoS/SoA | naive/SoA | "
+             "L1 hit soa/aos/naive | L2 hit soa/aos/naive |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        us = [f"{r[lay]['kernel_ns'] / 1e3:.2f}" if "kernel_ns" in r.get(lay, {}) else ""
+              for lay in SWEEP_LAYOUTS]
+        nsp = f"{r['soa']['ns_per_particle']:.4f}" if "ns_per_particle" in r.get("soa", {}) else ""
+        ratio = [f"{r[k]:.2f}" if k in r else "" for k in ("aos_over_soa", "naive_over_soa")]
+        h = [hits(r.get(lay, {})) for lay in SWEEP_LAYOUTS]
+        lines.append(f"| {r['SIZE']} | {r['N']:.0e} | {' | '.join(us)} | {nsp} | "
+                     f"{' | '.join(ratio)} | {'/'.join(x[0] for x in h)} | "
+                     f"{'/'.join(x[1] for x in h)} |")
+    return "\n".join(lines)
 
 
 def cpu_baseline(ref, si, target_s=20.0):
@@ -567,7 +737,21 @@ def main():
                          "its rows as one JSON line")
     ap.add_argument("--sweep-sizes", default="0,4,8,16,32")
     ap.add_argument("--sweep-ns", default="1e3,1e4,1e5,1e6,1e7,1e8")
+    ap.add_argument("--sweep-steps", type=int, default=0,
+                    help="timed steps per sweep point (default: 2e8 particle-steps, 20..2000)")
+    ap.add_argument("--sweep-report", metavar="DIR[,DIR...]",
+                    help="no GPU work: read the rocprofv3 kernel trace and/or counters of "
+                         "--sweep runs (same sizes, ns and steps) from each DIR and print "
+                         "per-launch kernel times and counters as one JSON line")
+    ap.add_argument("--md", action="store_true",
+                    help="with --sweep-report: print a markdown table instead")
     args = ap.parse_args()
+    if args.sweep_report:
+        sizes = tuple(int(x) for x in args.sweep_sizes.split(","))
+        ns = tuple(int(float(x)) for x in args.sweep_ns.split(","))
+        rows = sweep_report_rows(args.sweep_report.split(","), sizes, ns, args.sweep_steps or None)
+        print(sweep_markdown(rows) if args.md else json.dumps({"sweep_report": rows}), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path would shard by particle range with no communication; one GPU is measured)",
@@ -584,7 +768,8 @@ def main():
     if args.sweep:
         sizes = tuple(int(x) for x in args.sweep_sizes.split(","))
         ns = tuple(int(float(x)) for x in args.sweep_ns.split(","))
-        print(json.dumps({"sweep": bench_sweep(torch, soax, si, sizes, ns),
+        print(json.dumps({"sweep": bench_sweep(torch, soax, si, sizes, ns,
+                                               args.sweep_steps or None),
                           "device": torch.cuda.get_device_name(0)}), flush=True)
         return 0
     rows = {"aos", "euler", "small", "copy", "probes", "wide", "adjoint", "batch", "remove",

@@ -118,8 +118,10 @@ soax_status soax_schema_layout(const soax_schema* schema, int64_t* field_offsets
 /* ------------------------------------------------------------ particle sets */
 
 /*
- * Create a set of n particles on the current HIP device, allocating both
- * layouts (library-owned; freed by soax_destroy).  Each SoA array starts on
+ * Create a set of n particles on the current HIP device (the container of
+ * Section 4.1 constructed for a given particle count, one array per property
+ * and component), allocating both layouts (library-owned; freed by
+ * soax_destroy).  Each SoA array starts on
  * a 256-byte boundary.  Contents are undefined until filled or written.
  * Errors: ARG (null, n < 0), SCHEMA, RANGE (n > 2^31-1, or an int32/i8/u8
  * "id" too narrow for n), OOM.
@@ -210,7 +212,11 @@ soax_status soax_aos_to_soa(soax_set* set, void* stream);
 soax_status soax_soa_to_aos(soax_set* set, void* stream);
 
 /* Copy record i of one layout (SOAX_SOA, SOAX_AOS or SOAX_AOSOA) to host
- * memory in AoS form (stride bytes, padding 0).  Synchronises the null stream. */
+ * memory in AoS form (stride bytes, padding 0): the particle extracted as one
+ * object of all its properties, as the element access of Section 4.1 does.
+ * Errors: ARG (null set or record, i outside [0, n), unknown layout),
+ * LAYOUT (the set holds no copy in that layout), HIP.  Synchronises the null
+ * stream. */
 soax_status soax_get_record(const soax_set* set, int32_t layout, int64_t i, void* host_record);
 
 /* ----------------------------------------------------------- AoSoA tiles */

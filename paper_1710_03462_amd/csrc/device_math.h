@@ -174,6 +174,110 @@ __device__ __forceinline__ void st1(T* p, T v) {
   else *p = v;
 }
 
+// ------------------------------------------------ streaming through buffers
+//
+// The streaming kernels address each array through a buffer resource that
+// covers one workgroup's run of elements, because buffer loads and stores
+// carry the full set of gfx950 cache-policy bits (bit 0 sc0, bit 1 nt,
+// bit 4 sc1), where plain global accesses reach only nt.  Loads are nt (the
+// data is not reused); stores are nt at system scope (sc0 sc1 nt), which
+// writes them through without keeping them in the caches.  Measured at 1e8
+// particles against nt loads and stores through global pointers: Euler step
+// 0.91 -> 0.88 ms, RK2 step 1.05 -> 1.02 ms.  The offsets are 32-bit and
+// small (one workgroup's run), and every access is in range: the kernels
+// take the buffer path only for whole runs.
+constexpr int kPolicyLoadStream = 2;    // nt
+constexpr int kPolicyStoreStream = 19;  // sc0 | nt | sc1
+// Word 3 of an unformatted buffer resource on the gfx9 family.
+constexpr int kRsrcWord3 = 0x00020000;
+
+template <typename T>
+struct Window {
+  __amdgpu_buffer_rsrc_t r;
+};
+
+// count elements of base starting at element first (count * sizeof(T) < 2^31)
+template <typename T>
+__device__ __forceinline__ Window<T> window(const T* base, int64_t first, int64_t count) {
+  return Window<T>{__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base) + first, 0,
+                                                     static_cast<int>(count * sizeof(T)),
+                                                     kRsrcWord3)};
+}
+
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+template <int BYTES>
+struct RawChunk;
+template <>
+struct RawChunk<4> {
+  using V = unsigned int;
+  __device__ static V ld(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kPolicyLoadStream);
+  }
+  __device__ static void st(V v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, kPolicyStoreStream);
+  }
+};
+template <>
+struct RawChunk<8> {
+  using V = u32x2_t;
+  __device__ static V ld(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kPolicyLoadStream);
+  }
+  __device__ static void st(V v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, kPolicyStoreStream);
+  }
+};
+template <>
+struct RawChunk<16> {
+  using V = u32x4_t;
+  __device__ static V ld(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kPolicyLoadStream);
+  }
+  __device__ static void st(V v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, kPolicyStoreStream);
+  }
+};
+
+// VEC consecutive elements from element e of the window, as chunks of at most
+// 16 bytes (the same chunking as ld_run / st_run).
+template <typename T, int VEC>
+__device__ __forceinline__ void win_ld_run(Window<T> w, int e, T (&v)[VEC]) {
+  using C = RunChunk<T, VEC>;
+  using R = RawChunk<C::kBytes>;
+#pragma unroll
+  for (int c = 0; c < C::kChunks; ++c) {
+    const typename R::V t = R::ld(w.r, (e + c * C::kElems) * static_cast<int>(sizeof(T)));
+    __builtin_memcpy(&v[c * C::kElems], &t, C::kBytes);
+  }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void win_st_run(Window<T> w, int e, const T (&v)[VEC]) {
+  using C = RunChunk<T, VEC>;
+  using R = RawChunk<C::kBytes>;
+#pragma unroll
+  for (int c = 0; c < C::kChunks; ++c) {
+    typename R::V t;
+    __builtin_memcpy(&t, &v[c * C::kElems], C::kBytes);
+    R::st(t, w.r, (e + c * C::kElems) * static_cast<int>(sizeof(T)));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T win_ld1(Window<T> w, int e) {
+  T v[1];
+  win_ld_run<T, 1>(w, e, v);
+  return v[0];
+}
+
+template <typename T>
+__device__ __forceinline__ void win_st1(Window<T> w, int e, T x) {
+  const T v[1] = {x};
+  win_st_run<T, 1>(w, e, v);
+}
+
 template <typename T>
 __device__ __forceinline__ double widen(T v) {
   return static_cast<double>(v);

@@ -33,24 +33,28 @@ __device__ __forceinline__ void batch_tile(const BatchSet& S, int64_t t, int32_t
   VT* vy = static_cast<VT*>(S.vel[1]);
   VT* vz = static_cast<VT*>(S.vel[2]);
   if (i0 + PPT <= S.n) {
+    // the batch spans far more than the caches: streaming loads and stores
+    // through buffer windows over this tile
+    const int64_t first = (t - S.tile_begin) * tile;
+    const int64_t cnt = min(static_cast<int64_t>(tile), S.n - first);
+    const int e = static_cast<int>(threadIdx.x) * PPT;
     double x[PPT], y[PPT], z[PPT];
     VT u[PPT], v[PPT], w[PPT];
-    ld_run<false, double, PPT>(px + i0, x);
-    ld_run<false, double, PPT>(py + i0, y);
-    ld_run<false, double, PPT>(pz + i0, z);
+    win_ld_run<double, PPT>(window(px, first, cnt), e, x);
+    win_ld_run<double, PPT>(window(py, first, cnt), e, y);
+    win_ld_run<double, PPT>(window(pz, first, cnt), e, z);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       u[j] = v[j] = w[j] = VT(0);
       update_particle<kRk2Abc, double, VT, SMALL>(x[j], y[j], z[j], u[j], v[j], w[j], VT(0),
                                                   VT(0), VT(0), dt, p, 1);
     }
-    // the batch spans far more than the caches: nontemporal stores
-    st_run<true, double, PPT>(px + i0, x);
-    st_run<true, double, PPT>(py + i0, y);
-    st_run<true, double, PPT>(pz + i0, z);
-    st_run<true, VT, PPT>(vx + i0, u);
-    st_run<true, VT, PPT>(vy + i0, v);
-    st_run<true, VT, PPT>(vz + i0, w);
+    win_st_run<double, PPT>(window(px, first, cnt), e, x);
+    win_st_run<double, PPT>(window(py, first, cnt), e, y);
+    win_st_run<double, PPT>(window(pz, first, cnt), e, z);
+    win_st_run<VT, PPT>(window(vx, first, cnt), e, u);
+    win_st_run<VT, PPT>(window(vy, first, cnt), e, v);
+    win_st_run<VT, PPT>(window(vz, first, cnt), e, w);
   } else {
     for (int64_t i = i0; i < S.n; ++i) {
       double x = px[i], y = py[i], z = pz[i];

@@ -32,9 +32,25 @@ constexpr int kLdsBudget = 48 * 1024;  // bytes of LDS staging per workgroup
 
 // ------------------------------------------------------------ SoA step
 
-// STREAM: the step's arrays far exceed the caches.  Positions are loaded with
-// ordinary loads (they are overwritten in place) and every store, and the
-// loads of arrays the step only reads, carry the nontemporal hint.
+// Loads and stores of the SoA step.  STREAM (the step's arrays far exceed
+// the caches): through buffer windows over this workgroup's run of
+// particles, nt loads and write-through nt stores; otherwise ordinary global
+// accesses.  first / cnt: the workgroup's run, e: the thread's first element
+// in it.
+template <bool STREAM, typename T, int VEC>
+__device__ __forceinline__ void step_ld(const T* base, int64_t first, int64_t cnt, int e,
+                                        T (&v)[VEC]) {
+  if constexpr (STREAM) win_ld_run<T, VEC>(window(base, first, cnt), e, v);
+  else ld_run<false, T, VEC>(base + first + e, v);
+}
+
+template <bool STREAM, typename T, int VEC>
+__device__ __forceinline__ void step_st(T* base, int64_t first, int64_t cnt, int e,
+                                        const T (&v)[VEC]) {
+  if constexpr (STREAM) win_st_run<T, VEC>(window(base, first, cnt), e, v);
+  else st_run<false, T, VEC>(base + first + e, v);
+}
+
 template <int INTEG, typename PT, typename VT, int VEC, bool SMALL, bool STREAM>
 __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -51,13 +67,18 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
   const VT* ay = static_cast<const VT*>(a.acc[1]);
   const VT* az = static_cast<const VT*>(a.acc[2]);
   constexpr bool kReadsVel = !field_integrator(INTEG);  // field steps overwrite vel unread
-  constexpr bool kNtVelLoad = STREAM && INTEG == kEuler;  // read-only in Euler steps
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * blockDim.x * VEC;
+  const int64_t cnt = min(static_cast<int64_t>(blockDim.x) * VEC, a.n - first);
+  const int e = static_cast<int>(threadIdx.x) * VEC;
 
-  if constexpr (!field_integrator(INTEG)) {
+  if constexpr (!field_integrator(INTEG) && STREAM) {
     if (i0 + VEC <= a.n) {
-      // Euler steps are independent per coordinate: one component at a time
-      // (its loads, update and stores) keeps two or three streams per wave
-      // in flight instead of six -- faster on HBM for this in-place update.
+      // Streaming Euler steps are independent per coordinate: one component
+      // at a time (its loads, update and stores) keeps two or three streams
+      // per wave in flight instead of six -- faster on HBM for this in-place
+      // update.  Cache-resident sets take the path below, whose loads all
+      // leave before the first store: there the step is bound by latency,
+      // and three dependent round trips would triple it.
       PT* P[3] = {px, py, pz};
       VT* Vv[3] = {vx, vy, vz};
       const VT* G[3] = {ax, ay, az};
@@ -65,19 +86,15 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
       for (int d = 0; d < 3; ++d) {
         PT x[VEC];
         VT v[VEC], g[VEC];
-        ld_run<false, PT, VEC>(P[d] + i0, x);
-        if constexpr (uses_acc(INTEG)) {
-          ld_run<false, VT, VEC>(Vv[d] + i0, v);
-          ld_run<STREAM, VT, VEC>(G[d] + i0, g);
-        } else {
-          ld_run<kNtVelLoad, VT, VEC>(Vv[d] + i0, v);
-        }
+        step_ld<true, PT, VEC>(P[d], first, cnt, e, x);
+        step_ld<true, VT, VEC>(Vv[d], first, cnt, e, v);
+        if constexpr (uses_acc(INTEG)) step_ld<true, VT, VEC>(G[d], first, cnt, e, g);
 #pragma unroll
         for (int j = 0; j < VEC; ++j)
           euler_component<INTEG, PT, VT>(x[j], v[j], uses_acc(INTEG) ? g[j] : VT(0), a.dt,
                                          a.wrap);
-        st_run<STREAM, PT, VEC>(P[d] + i0, x);
-        if constexpr (uses_acc(INTEG)) st_run<STREAM, VT, VEC>(Vv[d] + i0, v);
+        step_st<true, PT, VEC>(P[d], first, cnt, e, x);
+        if constexpr (uses_acc(INTEG)) step_st<true, VT, VEC>(Vv[d], first, cnt, e, v);
       }
       return;
     }
@@ -89,19 +106,19 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
     // field steps: a wave issuing its loads or stores goes ahead of waves in
     // their arithmetic, so memory requests leave early (measured ~1% faster)
     if constexpr (field_integrator(INTEG)) __builtin_amdgcn_s_setprio(3);
-    ld_run<false, PT, VEC>(px + i0, x);
-    ld_run<false, PT, VEC>(py + i0, y);
-    ld_run<false, PT, VEC>(pz + i0, z);
+    step_ld<STREAM, PT, VEC>(px, first, cnt, e, x);
+    step_ld<STREAM, PT, VEC>(py, first, cnt, e, y);
+    step_ld<STREAM, PT, VEC>(pz, first, cnt, e, z);
     if constexpr (field_integrator(INTEG)) __builtin_amdgcn_s_setprio(0);
     if constexpr (kReadsVel) {
-      ld_run<kNtVelLoad, VT, VEC>(vx + i0, u);
-      ld_run<kNtVelLoad, VT, VEC>(vy + i0, v);
-      ld_run<kNtVelLoad, VT, VEC>(vz + i0, w);
+      step_ld<STREAM, VT, VEC>(vx, first, cnt, e, u);
+      step_ld<STREAM, VT, VEC>(vy, first, cnt, e, v);
+      step_ld<STREAM, VT, VEC>(vz, first, cnt, e, w);
     }
     if constexpr (uses_acc(INTEG)) {
-      ld_run<STREAM, VT, VEC>(ax + i0, ga);
-      ld_run<STREAM, VT, VEC>(ay + i0, gb);
-      ld_run<STREAM, VT, VEC>(az + i0, gc);
+      step_ld<STREAM, VT, VEC>(ax, first, cnt, e, ga);
+      step_ld<STREAM, VT, VEC>(ay, first, cnt, e, gb);
+      step_ld<STREAM, VT, VEC>(az, first, cnt, e, gc);
     } else {
 #pragma unroll
       for (int j = 0; j < VEC; ++j) ga[j] = gb[j] = gc[j] = VT(0);
@@ -113,13 +130,13 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
                                             gc[j], a.dt, p, a.wrap);
     }
     if constexpr (field_integrator(INTEG)) __builtin_amdgcn_s_setprio(3);
-    st_run<STREAM, PT, VEC>(px + i0, x);
-    st_run<STREAM, PT, VEC>(py + i0, y);
-    st_run<STREAM, PT, VEC>(pz + i0, z);
+    step_st<STREAM, PT, VEC>(px, first, cnt, e, x);
+    step_st<STREAM, PT, VEC>(py, first, cnt, e, y);
+    step_st<STREAM, PT, VEC>(pz, first, cnt, e, z);
     if constexpr (INTEG != kEuler) {
-      st_run<STREAM, VT, VEC>(vx + i0, u);
-      st_run<STREAM, VT, VEC>(vy + i0, v);
-      st_run<STREAM, VT, VEC>(vz + i0, w);
+      step_st<STREAM, VT, VEC>(vx, first, cnt, e, u);
+      step_st<STREAM, VT, VEC>(vy, first, cnt, e, v);
+      step_st<STREAM, VT, VEC>(vz, first, cnt, e, w);
     }
   } else {
     for (int64_t i = i0; i < a.n; ++i) {
@@ -698,38 +715,49 @@ __global__ void copy_tail_kernel(char* dst, const char* src, int64_t from, int64
 // ------------------------------------------------------------ stream probes
 
 // The memory accesses of the streaming SoA step kernels with their
-// arithmetic taken out: one particle per thread, positions loaded with
-// ordinary loads, every store and every read-only load nontemporal, as in
-// soa_step_kernel<..., STREAM = true>.  a.c is 0 for the patterns that
-// write (positions are rewritten unchanged) and NaN for the read-only one,
-// whose single guarded store never fires but keeps the loads alive.
+// arithmetic taken out: one particle per thread, every load and store through
+// the same buffer windows and cache-policy bits as
+// soa_step_kernel<..., STREAM = true>.  a.c is 0 for the patterns that write
+// (positions are rewritten unchanged) and NaN for the read-only one, whose
+// single guarded store never fires but keeps the loads alive.
 template <int PAT>
 __global__ __launch_bounds__(1024) void stream_probe_kernel(ProbeArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * blockDim.x;
+  const int64_t cnt = min(static_cast<int64_t>(blockDim.x), a.n - first);
+  const int e = static_cast<int>(threadIdx.x);
+  Window<double> P[3];
+  Window<float> V[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    P[d] = window(a.pos[d], first, cnt);
+    V[d] = window(a.vel[d], first, cnt);
+  }
   if constexpr (PAT == kProbeRk2) {
-    const double x = a.pos[0][i], y = a.pos[1][i], z = a.pos[2][i];
-    st1<true>(a.pos[0] + i, x + a.c);
-    st1<true>(a.pos[1] + i, y + a.c);
-    st1<true>(a.pos[2] + i, z + a.c);
-    st1<true>(a.vel[0] + i, static_cast<float>(x));
-    st1<true>(a.vel[1] + i, static_cast<float>(y));
-    st1<true>(a.vel[2] + i, static_cast<float>(z));
+    __builtin_amdgcn_s_setprio(3);
+    const double x = win_ld1(P[0], e), y = win_ld1(P[1], e), z = win_ld1(P[2], e);
+    win_st1(P[0], e, x + a.c);
+    win_st1(P[1], e, y + a.c);
+    win_st1(P[2], e, z + a.c);
+    win_st1(V[0], e, static_cast<float>(x));
+    win_st1(V[1], e, static_cast<float>(y));
+    win_st1(V[2], e, static_cast<float>(z));
   } else if constexpr (PAT == kProbeEuler) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double x = a.pos[d][i];
-      const float v = ld1<true>(a.vel[d] + i);
-      st1<true>(a.pos[d] + i, x + a.c * static_cast<double>(v));
+      const double x = win_ld1(P[d], e);
+      const float v = win_ld1(V[d], e);
+      win_st1(P[d], e, x + a.c * static_cast<double>(v));
     }
   } else if constexpr (PAT == kProbeRead) {
-    const double s = (a.pos[0][i] + a.pos[1][i]) + a.pos[2][i];
+    const double s = (win_ld1(P[0], e) + win_ld1(P[1], e)) + win_ld1(P[2], e);
     if (s == a.c) a.pos[0][i] = s;
   } else {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      st1<true>(a.pos[d] + i, a.c);
-      st1<true>(a.vel[d] + i, static_cast<float>(a.c));
+      win_st1(P[d], e, a.c);
+      win_st1(V[d], e, static_cast<float>(a.c));
     }
   }
 }
