@@ -186,7 +186,9 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
 /*
  * Override the launch shape of soax_step for one layout: block threads
  * (64..1024, multiple of 64) and particles per thread (1, 2 or 4; SoA only).
- * 0 restores the default.  Results do not depend on the shape.
+ * 0 restores the default: 128 threads (256 for the AoS layouts), one particle
+ * per thread, two for SOAX_RK2_ABC steps of SoA arrays that are 16-byte
+ * aligned.  Results do not depend on the shape.
  */
 soax_status soax_step_config(soax_set* set, int32_t layout, int32_t block, int32_t per_thread);
 

@@ -48,18 +48,23 @@ __device__ __forceinline__ Trig3 trig3(double x, double y, double z) {
 }
 
 // The same for the point (x + dx, y + dy, z + dz), from the values at (x, y, z).
-// SMALL: the caller guarantees every shift is at most trig::kShiftMax.
-template <bool SMALL>
+// TIER: what the caller guarantees about every shift (trig::kTierSmall,
+// kTierMid or kTierAny).
+template <int TIER>
 __device__ __forceinline__ Trig3 trig3_shift(const Trig3& t, double x, double y, double z,
                                              double dx, double dy, double dz) {
   Trig3 r;
-  trig::sincos_shift<!SMALL>(x, t.sx, t.cx, dx, &r.sx, &r.cx);
-  trig::sincos_shift<!SMALL>(y, t.sy, t.cy, dy, &r.sy, &r.cy);
-  trig::sincos_shift<!SMALL>(z, t.sz, t.cz, dz, &r.sz, &r.cz);
+  trig::sincos_shift<TIER>(x, t.sx, t.cx, dx, &r.sx, &r.cx);
+  trig::sincos_shift<TIER>(y, t.sy, t.cy, dy, &r.sy, &r.cy);
+  trig::sincos_shift<TIER>(z, t.sz, t.cz, dz, &r.sz, &r.cz);
   return r;
 }
 
 static_assert(kShiftLimit == trig::kShiftMax, "small_steps must match the shift bound");
+static_assert(kShiftMidLimit < trig::kShiftLong, "the mid tier must stay inside the long series");
+static_assert(kTierSmall == trig::kTierSmall && kTierMid == trig::kTierMid &&
+                  kTierAny == trig::kTierAny,
+              "shift tiers of the host and the device must agree");
 
 // u = (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x), each
 // component one product and one fused multiply-add
@@ -78,7 +83,7 @@ __device__ __forceinline__ void abc_field(const Abc& p, double x, double y, doub
 // One explicit-midpoint step: k1 = u(x), xm = x + (dt/2) k1, k2 = u(xm),
 // x+ = x + dt k2.  On return x holds x+ (not wrapped), t the sines and
 // cosines at the start point and d = dt k2 the displacement.
-template <bool SMALL>
+template <int TIER>
 __device__ __forceinline__ void rk2_midpoint_parts(const Abc& p, double dt, double& x, double& y,
                                                    double& z, Trig3& t, double& d0, double& d1,
                                                    double& d2) {
@@ -86,7 +91,7 @@ __device__ __forceinline__ void rk2_midpoint_parts(const Abc& p, double dt, doub
   double k0, k1, k2;
   field_of(p, t, k0, k1, k2);
   const double h = 0.5 * dt;
-  const Trig3 tm = trig3_shift<SMALL>(t, x, y, z, h * k0, h * k1, h * k2);
+  const Trig3 tm = trig3_shift<TIER>(t, x, y, z, h * k0, h * k1, h * k2);
   field_of(p, tm, k0, k1, k2);
   d0 = dt * k0;
   d1 = dt * k1;
@@ -301,13 +306,13 @@ __device__ __forceinline__ void euler_component(PT& x, VT& v, VT a, double dt, i
 
 // One Heun step (explicit trapezoid): k1 = u(x), k2 = u(x + dt k1),
 // d = (dt/2)(k1 + k2); t holds the start point's sines and cosines.
-template <bool SMALL>
+template <int TIER>
 __device__ __forceinline__ void heun_parts(const Abc& p, double dt, double x, double y, double z,
                                            Trig3& t, double& d0, double& d1, double& d2) {
   t = trig3(x, y, z);
   double a0, a1, a2, b0, b1, b2;
   field_of(p, t, a0, a1, a2);
-  field_of(p, trig3_shift<SMALL>(t, x, y, z, dt * a0, dt * a1, dt * a2), b0, b1, b2);
+  field_of(p, trig3_shift<TIER>(t, x, y, z, dt * a0, dt * a1, dt * a2), b0, b1, b2);
   const double h = 0.5 * dt;
   d0 = h * (a0 + b0);
   d1 = h * (a1 + b1);
@@ -317,16 +322,16 @@ __device__ __forceinline__ void heun_parts(const Abc& p, double dt, double x, do
 // One classical RK4 step: k1 = u(x), k2 = u(x + dt/2 k1), k3 = u(x + dt/2 k2),
 // k4 = u(x + dt k3), d = dt/6 (k1 + 2 k2 + 2 k3 + k4); every stage's sines come
 // from the start point's by angle addition.
-template <bool SMALL>
+template <int TIER>
 __device__ __forceinline__ void rk4_parts(const Abc& p, double dt, double x, double y, double z,
                                           Trig3& t, double& d0, double& d1, double& d2) {
   t = trig3(x, y, z);
   const double h = 0.5 * dt;
   double k10, k11, k12, k20, k21, k22, k30, k31, k32, k40, k41, k42;
   field_of(p, t, k10, k11, k12);
-  field_of(p, trig3_shift<SMALL>(t, x, y, z, h * k10, h * k11, h * k12), k20, k21, k22);
-  field_of(p, trig3_shift<SMALL>(t, x, y, z, h * k20, h * k21, h * k22), k30, k31, k32);
-  field_of(p, trig3_shift<SMALL>(t, x, y, z, dt * k30, dt * k31, dt * k32), k40, k41, k42);
+  field_of(p, trig3_shift<TIER>(t, x, y, z, h * k10, h * k11, h * k12), k20, k21, k22);
+  field_of(p, trig3_shift<TIER>(t, x, y, z, h * k20, h * k21, h * k22), k30, k31, k32);
+  field_of(p, trig3_shift<TIER>(t, x, y, z, dt * k30, dt * k31, dt * k32), k40, k41, k42);
   const double s = dt / 6.0;
   d0 = s * (k10 + 2.0 * k20 + 2.0 * k30 + k40);
   d1 = s * (k11 + 2.0 * k21 + 2.0 * k31 + k41);
@@ -334,8 +339,9 @@ __device__ __forceinline__ void rk4_parts(const Abc& p, double dt, double x, dou
 }
 
 // Advance one particle.  Positions and velocities are widened to double,
-// combined in double and rounded back on store.  SMALL: small_steps holds.
-template <int INTEG, typename PT, typename VT, bool SMALL>
+// combined in double and rounded back on store.  TIER: shift_tier of the
+// step (field integrators only; the results do not depend on it).
+template <int INTEG, typename PT, typename VT, int TIER>
 __device__ __forceinline__ void update_particle(PT& x0, PT& x1, PT& x2, VT& v0, VT& v1, VT& v2,
                                                 VT a0, VT a1, VT a2, double dt, const Abc& p,
                                                 int wrap) {
@@ -368,10 +374,10 @@ __device__ __forceinline__ void update_particle(PT& x0, PT& x1, PT& x2, VT& v0, 
     Trig3 t;
     double d0, d1, d2;
     if constexpr (INTEG == kRk2Abc) {
-      rk2_midpoint_parts<SMALL>(p, dt, y0, y1, y2, t, d0, d1, d2);
+      rk2_midpoint_parts<TIER>(p, dt, y0, y1, y2, t, d0, d1, d2);
     } else {
-      if constexpr (INTEG == kHeunAbc) heun_parts<SMALL>(p, dt, s0, s1, s2, t, d0, d1, d2);
-      else rk4_parts<SMALL>(p, dt, s0, s1, s2, t, d0, d1, d2);
+      if constexpr (INTEG == kHeunAbc) heun_parts<TIER>(p, dt, s0, s1, s2, t, d0, d1, d2);
+      else rk4_parts<TIER>(p, dt, s0, s1, s2, t, d0, d1, d2);
       y0 = s0 + d0;
       y1 = s1 + d1;
       y2 = s2 + d2;
@@ -387,7 +393,7 @@ __device__ __forceinline__ void update_particle(PT& x0, PT& x1, PT& x2, VT& v0, 
     // the stored velocity is the field at the new position (the field is
     // 2pi-periodic, so the shift from the start point needs no wrap)
     double u0, u1, u2;
-    field_of(p, trig3_shift<SMALL>(t, s0, s1, s2, d0, d1, d2), u0, u1, u2);
+    field_of(p, trig3_shift<TIER>(t, s0, s1, s2, d0, d1, d2), u0, u1, u2);
     v0 = static_cast<VT>(u0);
     v1 = static_cast<VT>(u1);
     v2 = static_cast<VT>(u2);

@@ -114,7 +114,7 @@ soax_status upload_params(soax_batch* b, const double* dt, const double* abc, hi
     b->stage_pending = false;
   }
   for (size_t i = 0; i < b->sets.size(); ++i) {
-    b->stage[i].small = small_steps(dt[i], abc[3 * i], abc[3 * i + 1], abc[3 * i + 2]) ? 1 : 0;
+    b->stage[i].tier = shift_tier(dt[i], abc[3 * i], abc[3 * i + 1], abc[3 * i + 2]);
     b->stage[i].dt = dt[i];
     b->stage[i].A = abc[3 * i];
     b->stage[i].B = abc[3 * i + 1];

@@ -39,6 +39,10 @@ constexpr int kTapeRows = 9;
 // Larger steps reduce every state in full.
 constexpr int64_t kAnchor = 16;
 
+// The angle-shift tier of these kernels: SMALL (small_steps holds) or any shift.
+template <bool SMALL>
+constexpr int kTierOf = SMALL ? kTierSmall : kTierAny;
+
 // One explicit-midpoint step from (x, y, z) with sines and cosines t, no
 // wrap; on return (x, y, z) is the state of step s + 1 and t its sines and
 // cosines as above.  (dt/2) k1 and dt k2 are the fields of the amplitudes
@@ -48,13 +52,13 @@ __device__ __forceinline__ void rk2_advance(const Abc& p, double dt, int64_t s, 
                                             double& y, double& z, Trig3& t) {
   double m0, m1, m2;
   field_of(scaled(p, 0.5 * dt), t, m0, m1, m2);
-  const Trig3 tm = trig3_shift<SMALL>(t, x, y, z, m0, m1, m2);
+  const Trig3 tm = trig3_shift<kTierOf<SMALL>>(t, x, y, z, m0, m1, m2);
   field_of(scaled(p, dt), tm, m0, m1, m2);
   const double x1 = x + m0, y1 = y + m1, z1 = z + m2;
   if (!SMALL || (s + 1) % kAnchor == 0)
     t = trig3(x1, y1, z1);
   else
-    t = trig3_shift<SMALL>(t, x, y, z, x1 - x, y1 - y, z1 - z);
+    t = trig3_shift<kTierOf<SMALL>>(t, x, y, z, x1 - x, y1 - y, z1 - z);
   x = x1;
   y = y1;
   z = z1;
@@ -106,7 +110,7 @@ __device__ __forceinline__ void rk2_reverse(const Abc& p, double dt, const Trig3
   const double h = 0.5 * dt;
   double h0, h1, h2;  // (dt/2) u(x), as in the forward step
   field_of(scaled(p, h), t, h0, h1, h2);
-  const Trig3 m = trig3_shift<SMALL>(t, x, y, z, h0, h1, h2);  // at xm
+  const Trig3 m = trig3_shift<kTierOf<SMALL>>(t, x, y, z, h0, h1, h2);  // at xm
   // mu = dt J(xm)^T lam, each component an amplitude times one fused
   // difference; dt is folded into the amplitudes
   const double dA = dt * p.A, dB = dt * p.B, dC = dt * p.C;
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
             if (!SMALL || ts == a.nsteps - 1 || ts % kAnchor == kAnchor - 1)
               tj = trig3(sx[j], sy[j], sz[j]);
             else
-              tj = trig3_shift<SMALL>(tn, xn, yn, zn, sx[j] - xn, sy[j] - yn, sz[j] - zn);
+              tj = trig3_shift<kTierOf<SMALL>>(tn, xn, yn, zn, sx[j] - xn, sy[j] - yn, sz[j] - zn);
             rk2_reverse<SMALL>(p, dt, tj, sx[j], sy[j], sz[j], l0, l1, l2, g0, g1, g2);
             tn = tj;
             xn = sx[j];

@@ -20,8 +20,8 @@ namespace soax {
 
 namespace {
 
-// One tile of set S.  SMALL: small_steps holds for this set.
-template <typename VT, int PPT, bool SMALL>
+// One tile of set S.  TIER: shift_tier of this set.
+template <typename VT, int PPT, int TIER>
 __device__ __forceinline__ void batch_tile(const BatchSet& S, int64_t t, int32_t tile) {
   const Abc p{S.A, S.B, S.C};
   const double dt = S.dt;
@@ -46,7 +46,7 @@ __device__ __forceinline__ void batch_tile(const BatchSet& S, int64_t t, int32_t
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       u[j] = v[j] = w[j] = VT(0);
-      update_particle<kRk2Abc, double, VT, SMALL>(x[j], y[j], z[j], u[j], v[j], w[j], VT(0),
+      update_particle<kRk2Abc, double, VT, TIER>(x[j], y[j], z[j], u[j], v[j], w[j], VT(0),
                                                   VT(0), VT(0), dt, p, 1);
     }
     win_st_run<double, PPT>(window(px, first, cnt), e, x);
@@ -59,7 +59,7 @@ __device__ __forceinline__ void batch_tile(const BatchSet& S, int64_t t, int32_t
     for (int64_t i = i0; i < S.n; ++i) {
       double x = px[i], y = py[i], z = pz[i];
       VT u = VT(0), v = VT(0), w = VT(0);
-      update_particle<kRk2Abc, double, VT, SMALL>(x, y, z, u, v, w, VT(0), VT(0), VT(0), dt, p,
+      update_particle<kRk2Abc, double, VT, TIER>(x, y, z, u, v, w, VT(0), VT(0), VT(0), dt, p,
                                                   1);
       px[i] = x;
       py[i] = y;
@@ -71,18 +71,22 @@ __device__ __forceinline__ void batch_tile(const BatchSet& S, int64_t t, int32_t
   }
 }
 
-// Every tile takes the unchecked angle-shift path when its own set's step
-// is provably small, the checked one otherwise (a branch uniform over the
-// workgroup, which works on one tile at a time).
+// Every tile takes the angle-shift path of its own set's tier (a branch
+// uniform over the workgroup, which works on one tile at a time).
+template <typename VT, int PPT>
+__device__ __forceinline__ void batch_tile_any(const BatchSet& S, int64_t t, int32_t tile) {
+  if (S.tier == kTierSmall)
+    batch_tile<VT, PPT, kTierSmall>(S, t, tile);
+  else if (S.tier == kTierMid)
+    batch_tile<VT, PPT, kTierMid>(S, t, tile);
+  else
+    batch_tile<VT, PPT, kTierAny>(S, t, tile);
+}
+
 template <typename VT, int PPT>
 __global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
-  for (int64_t t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
-    const BatchSet& S = b.sets[b.tile_set[t]];
-    if (S.small)
-      batch_tile<VT, PPT, true>(S, t, b.tile);
-    else
-      batch_tile<VT, PPT, false>(S, t, b.tile);
-  }
+  for (int64_t t = blockIdx.x; t < b.ntiles; t += gridDim.x)
+    batch_tile_any<VT, PPT>(b.sets[b.tile_set[t]], t, b.tile);
 }
 
 // The same with one workgroup per tile (the grid covers the tile list).
@@ -92,11 +96,7 @@ template <typename VT, int PPT>
 __global__ __launch_bounds__(512) void batch_rk2_tile_kernel(BatchLaunch b) {
   const int64_t t = blockIdx.x;
   if (t >= b.ntiles) return;
-  const BatchSet& S = b.sets[b.tile_set[t]];
-  if (S.small)
-    batch_tile<VT, PPT, true>(S, t, b.tile);
-  else
-    batch_tile<VT, PPT, false>(S, t, b.tile);
+  batch_tile_any<VT, PPT>(b.sets[b.tile_set[t]], t, b.tile);
 }
 
 template <typename VT, int PPT>

@@ -51,7 +51,7 @@ __device__ __forceinline__ void step_st(T* base, int64_t first, int64_t cnt, int
   else st_run<false, T, VEC>(base + first + e, v);
 }
 
-template <int INTEG, typename PT, typename VT, int VEC, bool SMALL, bool STREAM>
+template <int INTEG, typename PT, typename VT, int VEC, int TIER, bool STREAM>
 __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t i0 = t * VEC;
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
 #pragma unroll
     for (int j = 0; j < VEC; ++j) {
       if constexpr (!kReadsVel) u[j] = v[j] = w[j] = VT(0);
-      update_particle<INTEG, PT, VT, SMALL>(x[j], y[j], z[j], u[j], v[j], w[j], ga[j], gb[j],
+      update_particle<INTEG, PT, VT, TIER>(x[j], y[j], z[j], u[j], v[j], w[j], ga[j], gb[j],
                                             gc[j], a.dt, p, a.wrap);
     }
     if constexpr (field_integrator(INTEG)) __builtin_amdgcn_s_setprio(3);
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
         g1 = ay[i];
         g2 = az[i];
       }
-      update_particle<INTEG, PT, VT, SMALL>(x, y, z, u, v, w, g0, g1, g2, a.dt, p, a.wrap);
+      update_particle<INTEG, PT, VT, TIER>(x, y, z, u, v, w, g0, g1, g2, a.dt, p, a.wrap);
       px[i] = x;
       py[i] = y;
       pz[i] = z;
@@ -162,36 +162,36 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
   }
 }
 
-template <int INTEG, typename PT, typename VT, bool SMALL, bool STREAM>
+template <int INTEG, typename PT, typename VT, int TIER, bool STREAM>
 hipError_t soa_step_launch(int vec, int64_t grid, int block, const SoaStepArgs& a, hipStream_t s) {
   if constexpr (INTEG == kHeunAbc || INTEG == kRk4Abc) {
     // one particle per thread only (the host forces vec = 1 for these)
-    hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 1, SMALL, STREAM>), dim3(grid), dim3(block),
+    hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 1, TIER, STREAM>), dim3(grid), dim3(block),
                        0, s, a);
     return hipGetLastError();
   }
   switch (vec) {
     case 1:
-      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 1, SMALL, STREAM>), dim3(grid),
+      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 1, TIER, STREAM>), dim3(grid),
                          dim3(block), 0, s, a);
       break;
     case 2:
-      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 2, SMALL, STREAM>), dim3(grid),
+      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 2, TIER, STREAM>), dim3(grid),
                          dim3(block), 0, s, a);
       break;
     default:
-      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 4, SMALL, STREAM>), dim3(grid),
+      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 4, TIER, STREAM>), dim3(grid),
                          dim3(block), 0, s, a);
       break;
   }
   return hipGetLastError();
 }
 
-template <int INTEG, typename PT, typename VT, bool SMALL>
+template <int INTEG, typename PT, typename VT, int TIER>
 hipError_t soa_step_stream(bool stream, int vec, int64_t grid, int block, const SoaStepArgs& a,
                            hipStream_t s) {
-  return stream ? soa_step_launch<INTEG, PT, VT, SMALL, true>(vec, grid, block, a, s)
-                : soa_step_launch<INTEG, PT, VT, SMALL, false>(vec, grid, block, a, s);
+  return stream ? soa_step_launch<INTEG, PT, VT, TIER, true>(vec, grid, block, a, s)
+                : soa_step_launch<INTEG, PT, VT, TIER, false>(vec, grid, block, a, s);
 }
 
 template <int INTEG, typename PT, typename VT>
@@ -204,10 +204,13 @@ hipError_t soa_step_vec(int vec, int block, const SoaStepArgs& a, hipStream_t s)
   if (uses_acc(INTEG)) bytes += 3 * sizeof(VT);
   const bool stream = a.n * bytes >= kStreamBytes;
   if constexpr (field_integrator(INTEG)) {
-    if (small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C))
-      return soa_step_stream<INTEG, PT, VT, true>(stream, vec, grid, block, a, s);
+    const int tier = shift_tier(a.dt, a.abc.A, a.abc.B, a.abc.C);
+    if (tier == kTierSmall)
+      return soa_step_stream<INTEG, PT, VT, kTierSmall>(stream, vec, grid, block, a, s);
+    if (tier == kTierMid)
+      return soa_step_stream<INTEG, PT, VT, kTierMid>(stream, vec, grid, block, a, s);
   }
-  return soa_step_stream<INTEG, PT, VT, false>(stream, vec, grid, block, a, s);
+  return soa_step_stream<INTEG, PT, VT, kTierAny>(stream, vec, grid, block, a, s);
 }
 
 // ------------------------------------------------------- AoS element access
@@ -233,7 +236,7 @@ __device__ __forceinline__ void rec_store(char* p, T v) {
 }
 
 // Update the record at `rec` (in LDS or global memory) in place.
-template <int INTEG, typename PT, typename VT, bool ALIGNED, bool SMALL>
+template <int INTEG, typename PT, typename VT, bool ALIGNED, int TIER>
 __device__ __forceinline__ void update_record(char* rec, const AosStepArgs& a, const Abc& p) {
   char* P = rec + a.off_pos;
   char* V = rec + a.off_vel;
@@ -251,7 +254,7 @@ __device__ __forceinline__ void update_record(char* rec, const AosStepArgs& a, c
     g1 = rec_load<VT, ALIGNED>(G + sizeof(VT));
     g2 = rec_load<VT, ALIGNED>(G + 2 * sizeof(VT));
   }
-  update_particle<INTEG, PT, VT, SMALL>(x, y, z, u, v, w, g0, g1, g2, a.dt, p, a.wrap);
+  update_particle<INTEG, PT, VT, TIER>(x, y, z, u, v, w, g0, g1, g2, a.dt, p, a.wrap);
   rec_store<PT, ALIGNED>(P, x);
   rec_store<PT, ALIGNED>(P + sizeof(PT), y);
   rec_store<PT, ALIGNED>(P + 2 * sizeof(PT), z);
@@ -264,7 +267,8 @@ __device__ __forceinline__ void update_record(char* rec, const AosStepArgs& a, c
 
 // Copy `nbytes` from global `g` (16-byte aligned) into LDS with 16-byte
 // accesses, consecutive lanes on consecutive chunks; the remainder bytewise.
-// NT: nontemporal global accesses (see ld_run).
+// STREAM: the 16-byte chunks go through a buffer window over the tile with the
+// streaming cache policies (see Window).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Each thread issues up to kStageLoads chunk loads before it writes any of
@@ -272,17 +276,18 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // on one chunk at a time.
 constexpr int kStageLoads = 4;
 
-template <bool NT>
+template <bool STREAM>
 __device__ __forceinline__ void stage_in(char* lds, const char* g, int nbytes) {
   const int nchunk = nbytes >> 4;
   const u32x4* src = reinterpret_cast<const u32x4*>(g);
+  const Window<u32x4> w = window(src, 0, nchunk);
   u32x4* dst = reinterpret_cast<u32x4*>(lds);
   const int step = static_cast<int>(blockDim.x);
   for (int c0 = threadIdx.x; c0 < nchunk; c0 += kStageLoads * step) {
     u32x4 v[kStageLoads];
 #pragma unroll
     for (int j = 0; j < kStageLoads; ++j)
-      if (c0 + j * step < nchunk) v[j] = ld1<NT>(src + c0 + j * step);
+      if (c0 + j * step < nchunk) v[j] = STREAM ? win_ld1(w, c0 + j * step) : src[c0 + j * step];
 #pragma unroll
     for (int j = 0; j < kStageLoads; ++j)
       if (c0 + j * step < nchunk) dst[c0 + j * step] = v[j];
@@ -290,18 +295,22 @@ __device__ __forceinline__ void stage_in(char* lds, const char* g, int nbytes) {
   for (int b = (nchunk << 4) + threadIdx.x; b < nbytes; b += blockDim.x) lds[b] = g[b];
 }
 
-template <bool NT>
+template <bool STREAM>
 __device__ __forceinline__ void stage_out(char* g, const char* lds, int nbytes) {
   const int nchunk = nbytes >> 4;
   const u32x4* src = reinterpret_cast<const u32x4*>(lds);
   u32x4* dst = reinterpret_cast<u32x4*>(g);
-  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) st1<NT>(dst + c, src[c]);
+  const Window<u32x4> w = window(dst, 0, nchunk);
+  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) {
+    if constexpr (STREAM) win_st1(w, c, src[c]);
+    else dst[c] = src[c];
+  }
   for (int b = (nchunk << 4) + threadIdx.x; b < nbytes; b += blockDim.x) g[b] = lds[b];
 }
 
 // ------------------------------------------------------------- AoS steps
 
-template <int INTEG, typename PT, typename VT, bool ALIGNED, bool SMALL, bool STREAM>
+template <int INTEG, typename PT, typename VT, bool ALIGNED, int TIER, bool STREAM>
 __global__ __launch_bounds__(1024) void aos_step_kernel(AosStepArgs a, int tile) {
   extern __shared__ uint4 lds_u4[];
   char* lds = reinterpret_cast<char*>(lds_u4);
@@ -309,32 +318,32 @@ __global__ __launch_bounds__(1024) void aos_step_kernel(AosStepArgs a, int tile)
   const int nrec = static_cast<int>(min(static_cast<int64_t>(tile), a.n - r0));
   char* g = a.aos + r0 * a.stride;
   const int nbytes = nrec * a.stride;
-  stage_in<false>(lds, g, nbytes);  // rewritten in place below
+  stage_in<STREAM>(lds, g, nbytes);
   __syncthreads();
   const Abc p = to_abc(a.abc);
   for (int r = threadIdx.x; r < nrec; r += blockDim.x)
-    update_record<INTEG, PT, VT, ALIGNED, SMALL>(lds + r * a.stride, a, p);
+    update_record<INTEG, PT, VT, ALIGNED, TIER>(lds + r * a.stride, a, p);
   __syncthreads();
   stage_out<STREAM>(g, lds, nbytes);
 }
 
-template <int INTEG, typename PT, typename VT, bool ALIGNED, bool SMALL>
+template <int INTEG, typename PT, typename VT, bool ALIGNED, int TIER>
 __global__ __launch_bounds__(1024) void aos_naive_kernel(AosStepArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  update_record<INTEG, PT, VT, ALIGNED, SMALL>(a.aos + i * a.stride, a, to_abc(a.abc));
+  update_record<INTEG, PT, VT, ALIGNED, TIER>(a.aos + i * a.stride, a, to_abc(a.abc));
 }
 
-template <int INTEG, typename PT, typename VT, bool SMALL>
+template <int INTEG, typename PT, typename VT, int TIER>
 hipError_t aos_step_launch(bool aligned, bool naive, int block, const AosStepArgs& a,
                            hipStream_t s) {
   if (naive) {
     const int64_t grid = (a.n + block - 1) / block;
     if (aligned)
-      hipLaunchKernelGGL((aos_naive_kernel<INTEG, PT, VT, true, SMALL>), dim3(grid), dim3(block), 0,
+      hipLaunchKernelGGL((aos_naive_kernel<INTEG, PT, VT, true, TIER>), dim3(grid), dim3(block), 0,
                          s, a);
     else
-      hipLaunchKernelGGL((aos_naive_kernel<INTEG, PT, VT, false, SMALL>), dim3(grid), dim3(block),
+      hipLaunchKernelGGL((aos_naive_kernel<INTEG, PT, VT, false, TIER>), dim3(grid), dim3(block),
                          0, s, a);
   } else {
     const int tile = aos_tile_records(a.stride, block);
@@ -342,16 +351,16 @@ hipError_t aos_step_launch(bool aligned, bool naive, int block, const AosStepArg
     const size_t lds = (static_cast<size_t>(tile) * a.stride + 15) & ~static_cast<size_t>(15);
     const bool stream = a.n * a.stride >= kStreamBytes;
     if (aligned && stream)
-      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, true, SMALL, true>), dim3(grid),
+      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, true, TIER, true>), dim3(grid),
                          dim3(block), lds, s, a, tile);
     else if (aligned)
-      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, true, SMALL, false>), dim3(grid),
+      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, true, TIER, false>), dim3(grid),
                          dim3(block), lds, s, a, tile);
     else if (stream)
-      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, false, SMALL, true>), dim3(grid),
+      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, false, TIER, true>), dim3(grid),
                          dim3(block), lds, s, a, tile);
     else
-      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, false, SMALL, false>), dim3(grid),
+      hipLaunchKernelGGL((aos_step_kernel<INTEG, PT, VT, false, TIER, false>), dim3(grid),
                          dim3(block), lds, s, a, tile);
   }
   return hipGetLastError();
@@ -361,10 +370,13 @@ template <int INTEG, typename PT, typename VT>
 hipError_t aos_step_t(bool aligned, bool naive, int block, const AosStepArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   if constexpr (field_integrator(INTEG)) {
-    if (small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C))
-      return aos_step_launch<INTEG, PT, VT, true>(aligned, naive, block, a, s);
+    const int tier = shift_tier(a.dt, a.abc.A, a.abc.B, a.abc.C);
+    if (tier == kTierSmall)
+      return aos_step_launch<INTEG, PT, VT, kTierSmall>(aligned, naive, block, a, s);
+    if (tier == kTierMid)
+      return aos_step_launch<INTEG, PT, VT, kTierMid>(aligned, naive, block, a, s);
   }
-  return aos_step_launch<INTEG, PT, VT, false>(aligned, naive, block, a, s);
+  return aos_step_launch<INTEG, PT, VT, kTierAny>(aligned, naive, block, a, s);
 }
 
 template <int INTEG>
@@ -400,31 +412,40 @@ __device__ __forceinline__ void for_blocks(int b, int e, F&& f) {
   }
 }
 
-// Element i of arrays order[b..e) (element type T) into the record `rec`.
-template <typename T, bool ALIGNED, bool NT>
-__device__ __forceinline__ void gather_size(const XposeArgs& t, int b, int e, int64_t i,
-                                            char* rec) {
+// Element r0 + r of arrays order[b..e) (element type T) into the record
+// `rec`.  STREAM: through buffer windows over the tile's nrec elements of
+// each array, with the streaming cache policies.
+template <typename T, bool ALIGNED, bool STREAM>
+__device__ __forceinline__ void gather_size(const XposeArgs& t, int b, int e, int64_t r0,
+                                            int nrec, int r, char* rec) {
   for_blocks(b, e, [&](auto G, int a0) {
     T v[G.value];
 #pragma unroll
-    for (int j = 0; j < G.value; ++j)
-      v[j] = ld1<NT>(reinterpret_cast<const T*>(t.soa[t.order[a0 + j]]) + i);
+    for (int j = 0; j < G.value; ++j) {
+      const T* arr = reinterpret_cast<const T*>(t.soa[t.order[a0 + j]]);
+      if constexpr (STREAM) v[j] = win_ld1(window(arr, r0, nrec), r);
+      else v[j] = arr[r0 + r];
+    }
 #pragma unroll
     for (int j = 0; j < G.value; ++j) rec_store<T, ALIGNED>(rec + t.off[t.order[a0 + j]], v[j]);
   });
 }
 
-// The record `rec`'s fields of arrays order[b..e) into element i of each.
-template <typename T, bool ALIGNED, bool NT>
-__device__ __forceinline__ void scatter_size(const XposeArgs& t, int b, int e, int64_t i,
-                                             const char* rec) {
+// The record `rec`'s fields of arrays order[b..e) into element r0 + r of
+// each (STREAM as in gather_size).
+template <typename T, bool ALIGNED, bool STREAM>
+__device__ __forceinline__ void scatter_size(const XposeArgs& t, int b, int e, int64_t r0,
+                                             int nrec, int r, const char* rec) {
   for_blocks(b, e, [&](auto G, int a0) {
     T v[G.value];
 #pragma unroll
     for (int j = 0; j < G.value; ++j) v[j] = rec_load<T, ALIGNED>(rec + t.off[t.order[a0 + j]]);
 #pragma unroll
-    for (int j = 0; j < G.value; ++j)
-      st1<NT>(reinterpret_cast<T*>(t.soa[t.order[a0 + j]]) + i, v[j]);
+    for (int j = 0; j < G.value; ++j) {
+      T* arr = reinterpret_cast<T*>(t.soa[t.order[a0 + j]]);
+      if constexpr (STREAM) win_st1(window(arr, r0, nrec), r, v[j]);
+      else arr[r0 + r] = v[j];
+    }
   });
 }
 
@@ -445,9 +466,9 @@ __global__ __launch_bounds__(256) void aos_to_soa_kernel(const XposeArgs* __rest
   __syncthreads();
   for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
     const char* rec = lds + r * stride;
-    scatter_size<uint64_t, ALIGNED, STREAM>(t, 0, t.group_end[0], r0 + r, rec);
-    scatter_size<uint32_t, ALIGNED, STREAM>(t, t.group_end[0], t.group_end[1], r0 + r, rec);
-    scatter_size<uint8_t, ALIGNED, false>(t, t.group_end[1], t.group_end[2], r0 + r, rec);
+    scatter_size<uint64_t, ALIGNED, STREAM>(t, 0, t.group_end[0], r0, nrec, r, rec);
+    scatter_size<uint32_t, ALIGNED, STREAM>(t, t.group_end[0], t.group_end[1], r0, nrec, r, rec);
+    scatter_size<uint8_t, ALIGNED, false>(t, t.group_end[1], t.group_end[2], r0, nrec, r, rec);
   }
 }
 
@@ -469,9 +490,9 @@ __global__ __launch_bounds__(256) void soa_to_aos_kernel(const XposeArgs* __rest
   __syncthreads();
   for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
     char* rec = lds + r * stride;
-    gather_size<uint64_t, ALIGNED, STREAM>(t, 0, t.group_end[0], r0 + r, rec);
-    gather_size<uint32_t, ALIGNED, STREAM>(t, t.group_end[0], t.group_end[1], r0 + r, rec);
-    gather_size<uint8_t, ALIGNED, false>(t, t.group_end[1], t.group_end[2], r0 + r, rec);
+    gather_size<uint64_t, ALIGNED, STREAM>(t, 0, t.group_end[0], r0, nrec, r, rec);
+    gather_size<uint32_t, ALIGNED, STREAM>(t, t.group_end[0], t.group_end[1], r0, nrec, r, rec);
+    gather_size<uint8_t, ALIGNED, false>(t, t.group_end[1], t.group_end[2], r0, nrec, r, rec);
   }
   __syncthreads();
   stage_out<STREAM>(t.aos + r0 * stride, lds, nbytes);
@@ -558,7 +579,7 @@ __global__ __launch_bounds__(256) void aosoa_chunk_kernel(const XposeArgs* __res
   else *tile_p = *soa_p;
 }
 
-template <int INTEG, typename PT, typename VT, bool SMALL, bool STREAM>
+template <int INTEG, typename PT, typename VT, int TIER, bool STREAM>
 __global__ __launch_bounds__(1024) void aosoa_step_kernel(AosoaStepArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
@@ -586,7 +607,7 @@ __global__ __launch_bounds__(1024) void aosoa_step_kernel(AosoaStepArgs a) {
   } else {
     PT x = ld1<false>(P[0]), y = ld1<false>(P[1]), z = ld1<false>(P[2]);
     VT u = VT(0), v = VT(0), w = VT(0);
-    update_particle<INTEG, PT, VT, SMALL>(x, y, z, u, v, w, VT(0), VT(0), VT(0), a.dt, p, a.wrap);
+    update_particle<INTEG, PT, VT, TIER>(x, y, z, u, v, w, VT(0), VT(0), VT(0), a.dt, p, a.wrap);
     st1<STREAM>(P[0], x);
     st1<STREAM>(P[1], y);
     st1<STREAM>(P[2], z);
@@ -602,14 +623,16 @@ hipError_t aosoa_step_t(int block, const AosoaStepArgs& a, hipStream_t s) {
   int64_t bytes = 3 * (sizeof(PT) + sizeof(VT));
   if (uses_acc(INTEG)) bytes += 3 * sizeof(VT);
   const bool stream = a.n * bytes >= kStreamBytes;
-  bool small = false;
-  if constexpr (field_integrator(INTEG)) small = small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C);
-#define SOAX_AOSOA(SM, ST) \
-  hipLaunchKernelGGL((aosoa_step_kernel<INTEG, PT, VT, SM, ST>), dim3(grid), dim3(block), 0, s, a)
-  if (small && stream) SOAX_AOSOA(true, true);
-  else if (small) SOAX_AOSOA(true, false);
-  else if (stream) SOAX_AOSOA(false, true);
-  else SOAX_AOSOA(false, false);
+  int tier = kTierAny;
+  if constexpr (field_integrator(INTEG)) tier = shift_tier(a.dt, a.abc.A, a.abc.B, a.abc.C);
+#define SOAX_AOSOA(TI, ST) \
+  hipLaunchKernelGGL((aosoa_step_kernel<INTEG, PT, VT, TI, ST>), dim3(grid), dim3(block), 0, s, a)
+  if (tier == kTierSmall && stream) SOAX_AOSOA(kTierSmall, true);
+  else if (tier == kTierSmall) SOAX_AOSOA(kTierSmall, false);
+  else if (tier == kTierMid && stream) SOAX_AOSOA(kTierMid, true);
+  else if (tier == kTierMid) SOAX_AOSOA(kTierMid, false);
+  else if (stream) SOAX_AOSOA(kTierAny, true);
+  else SOAX_AOSOA(kTierAny, false);
 #undef SOAX_AOSOA
   return hipGetLastError();
 }
@@ -697,14 +720,20 @@ __global__ __launch_bounds__(256) void vel_from_field_kernel(SoaStepArgs a) {
 
 // ------------------------------------------------------------------- copy
 
-// One 16-byte element per thread, nontemporal loads and stores: the fastest
-// streaming form measured on the MI355X (a grid-stride loop or several
-// elements per thread keep fewer independent requests in flight per CU).
+// One 16-byte element per thread, moved through buffer windows over the
+// workgroup's run with the streaming cache policies of the step kernels: the
+// fastest streaming form measured on the MI355X (a grid-stride loop or
+// several elements per thread keep fewer independent requests in flight per
+// CU).
 
 __global__ __launch_bounds__(256) void copy16_kernel(u32x4* __restrict__ dst,
                                                      const u32x4* __restrict__ src, int64_t n16) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+  if (i >= n16) return;
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * blockDim.x;
+  const int64_t cnt = min(static_cast<int64_t>(blockDim.x), n16 - first);
+  const int e = static_cast<int>(threadIdx.x);
+  win_st1(window(dst, first, cnt), e, win_ld1(window(src, first, cnt), e));
 }
 
 __global__ void copy_tail_kernel(char* dst, const char* src, int64_t from, int64_t bytes) {

@@ -49,6 +49,22 @@ inline __host__ __device__ bool small_steps(double dt, double A, double B, doubl
   return (dt < 0 ? -dt : dt) * s <= kShiftLimit;
 }
 
+// What the host proves about every displacement of a step of the field
+// integrators (the shift of the angle additions): kTierSmall, every shift at
+// most kShiftLimit; kTierMid, every shift at most 1/8 (the longer series of
+// the angle addition, checked against kShiftMidLimit, 1/8 less 2^-20 of it,
+// so that no rounding of dt u can carry a shift past 1/8); kTierAny, no
+// bound.  A kernel instantiated for a tier gives exactly the results of the
+// kTierAny kernel on every step that satisfies the tier's bound.
+enum ShiftTier : int32_t { kTierSmall = 0, kTierMid = 1, kTierAny = 2 };
+constexpr double kShiftMidLimit = 0.125 * (1.0 - 0x1p-20);
+
+inline __host__ __device__ int shift_tier(double dt, double A, double B, double C) {
+  const double s = (A < 0 ? -A : A) + (B < 0 ? -B : B) + (C < 0 ? -C : C);
+  const double m = (dt < 0 ? -dt : dt) * s;
+  return m <= kShiftLimit ? kTierSmall : (m <= kShiftMidLimit ? kTierMid : kTierAny);
+}
+
 // A step whose arrays span at least this many bytes streams through HBM and
 // uses nontemporal hints; smaller working sets stay cache-resident between
 // steps and use ordinary accesses.
@@ -312,7 +328,7 @@ struct BatchSet {
   int64_t tile_begin;  // first tile of this set in the batch's tile list
   double dt;
   double A, B, C;
-  int32_t small;  // small_steps holds for this set's dt and amplitudes
+  int32_t tier;   // shift_tier of this set's dt and amplitudes
   int32_t reserved;
 };
 

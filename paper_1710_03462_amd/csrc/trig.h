@@ -140,16 +140,23 @@ constexpr double kShiftLong = 1.0 / 8;
 constexpr double T3 = -inv_fact(7), T4 = inv_fact(9);
 constexpr double U3 = inv_fact(8), U4 = -inv_fact(10);
 
-// CHECKED = false: the caller guarantees |d| <= kShiftMax.  CHECKED = true:
-// any d; 1/64 < |d| <= 1/8 takes the longer series, larger shifts a full
-// reduction of x + d.
-template <bool CHECKED = true>
+// What the caller guarantees about the shift, by tier.  kTierSmall:
+// |d| <= kShiftMax (the short series alone).  kTierMid: |d| <= kShiftLong
+// (per lane, the short series up to kShiftMax and the longer one beyond).
+// kTierAny: any d (as kTierMid, and a full reduction of x + d beyond
+// kShiftLong).  Where its guarantee holds, each tier gives exactly the
+// results of kTierAny.
+constexpr int kTierSmall = 0;
+constexpr int kTierMid = 1;
+constexpr int kTierAny = 2;
+
+template <int TIER = kTierAny>
 __host__ __device__ __forceinline__ void sincos_shift(double x, double sx, double cx, double d,
                                                       double* s, double* c) {
   double sd, cm1;
   const double w = d * d;
-  if (CHECKED && !(fabs(d) <= kShiftMax)) {
-    if (!(fabs(d) <= kShiftLong)) {
+  if (TIER != kTierSmall && !(fabs(d) <= kShiftMax)) {
+    if (TIER == kTierAny && !(fabs(d) <= kShiftLong)) {
       sincos_fast(x + d, s, c);
       return;
     }

@@ -12,8 +12,8 @@ import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libtrig_device_check.so")
-KINDS = ["sin x", "cos x", "sin(x+d) unchecked", "cos(x+d) unchecked", "sin(x+e) checked",
-         "cos(x+e) checked"]
+KINDS = ["sin x", "cos x", "sin(x+d) small tier", "cos(x+d) small tier", "sin(x+e) any tier",
+         "cos(x+e) any tier", "sin(x+f) mid tier", "cos(x+f) mid tier"]
 
 pytestmark = pytest.mark.gpu
 
@@ -30,17 +30,17 @@ def check():
     return fn
 
 
-# ranges of the fast path (|x| <= 2^19); checked shifts up to 1/8 take the
-# longer series, up to 1/2 also the full reduction of x + e
+# ranges of the fast path (|x| <= 2^19); shifts up to 1/8 take the longer
+# series, any-tier shifts up to 1/2 also the full reduction of x + e
 @pytest.mark.parametrize("lo,hi", [(-1.0, 8.0), (-20.0, 20.0), (1e3, 1e4), (4e5, 5.2e5),
                                    (-5.2e5, -4e5), (-1e-3, 1e-3)])
 @pytest.mark.parametrize("emax", [1.0 / 64, 1.0 / 8, 0.5])
 def test_device_sincos_bit_equal_to_host(check, lo, hi, emax):
     n = 1 << 18
-    mism = np.zeros(6, dtype=np.int64)
-    first = np.zeros(6, dtype=np.float64)
+    mism = np.zeros(len(KINDS), dtype=np.int64)
+    first = np.zeros(len(KINDS), dtype=np.float64)
     print(f"trig_device_check n={n} range=({lo}, {hi}) emax={emax}", flush=True)
     rc = check(n, lo, hi, emax, 12345, mism.ctypes.data, first.ctypes.data)
     assert rc == 0, f"HIP error {rc}"
-    bad = {KINDS[k]: (int(mism[k]), float(first[k])) for k in range(6) if mism[k]}
+    bad = {KINDS[k]: (int(mism[k]), float(first[k])) for k in range(len(KINDS)) if mism[k]}
     assert not bad, bad

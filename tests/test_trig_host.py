@@ -44,6 +44,16 @@ def test_checked_shift_longer_series_within_one_ulp(exe, lo, hi):
     assert float(out[4]) <= 1.0 and float(out[5]) <= 1.0, out
 
 
+@pytest.mark.parametrize("shift_max", [1.0 / 64, 1.0 / 8, 0.5])
+def test_shift_tiers_equal_the_any_tier_inside_their_bounds(exe, shift_max):
+    # kTierSmall (|d| <= 1/64) and kTierMid (|d| <= 1/8) drop the range checks
+    # the host has proven unneeded; inside those bounds they must give the
+    # any-tier results bit for bit (last field: count of differing pairs)
+    out = subprocess.run([exe, "-20", "20", "400000", str(shift_max)], check=True,
+                         capture_output=True, text=True).stdout.split()
+    assert int(out[6]) == 0, out
+
+
 @pytest.mark.parametrize("lo,hi", [(-1.0, 8.0), (-20.0, 20.0)])
 def test_checked_shift_full_reduction_beyond_the_series(exe, lo, hi):
     # shifts up to 1/2 reach the full reduction of the rounded sum x + d: its

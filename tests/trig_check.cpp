@@ -48,6 +48,7 @@ int main(int argc, char** argv) {
   // shifted evaluation: sin/cos(x + d) from sin/cos(x), reference in long double;
   // the error is absolute, in units of ulp(1) = 2^-52
   double worst_ss = 0, worst_sc = 0;
+  long tier_mismatch = 0;
   for (long i = 0; i < n; ++i) {
     st += 0x9E3779B97F4A7C15ull;
     uint64_t z = st;
@@ -60,6 +61,16 @@ int main(int argc, char** argv) {
     double s, c, s2, c2;
     soax::trig::sincos_fast(x, &s, &c);
     soax::trig::sincos_shift(x, s, c, d, &s2, &c2);
+    // a tier whose bound holds gives exactly the any-tier results
+    double s3, c3;
+    if (fabs(d) <= soax::trig::kShiftLong) {
+      soax::trig::sincos_shift<soax::trig::kTierMid>(x, s, c, d, &s3, &c3);
+      if (s3 != s2 || c3 != c2) ++tier_mismatch;
+    }
+    if (fabs(d) <= soax::trig::kShiftMax) {
+      soax::trig::sincos_shift<soax::trig::kTierSmall>(x, s, c, d, &s3, &c3);
+      if (s3 != s2 || c3 != c2) ++tier_mismatch;
+    }
     const long double xl = (long double)x + (long double)d;
     const double rs = (double)sinl(xl), rc = (double)cosl(xl);
     // angle addition bounds the absolute error: measure it in ulps of 1
@@ -67,6 +78,7 @@ int main(int argc, char** argv) {
     if (es > worst_ss) worst_ss = es;
     if (ec > worst_sc) worst_sc = ec;
   }
-  printf("%.3f %.17g %.3f %.17g %.3f %.3f\n", worst_s, at_s, worst_c, at_c, worst_ss, worst_sc);
+  printf("%.3f %.17g %.3f %.17g %.3f %.3f %ld\n", worst_s, at_s, worst_c, at_c, worst_ss, worst_sc,
+         tier_mismatch);
   return 0;
 }

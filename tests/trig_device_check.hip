@@ -4,9 +4,9 @@
 // v_fma_f64 instructions; the host build of the same header evaluates them
 // with fma() calls.  Both are chains of correctly rounded fused multiply-adds
 // on the same operands, so the two must agree bit for bit.  This helper runs
-// sincos_fast, the unchecked sincos_shift (|d| <= 1/64) and the checked
-// sincos_shift (any d) on seeded arguments on the GPU and on the host and
-// counts the results whose bits differ.  Test infrastructure only: it is
+// sincos_fast and sincos_shift in each of its tiers (|d| <= 1/64; |f| below
+// 1/8; any e) on seeded arguments on the GPU and on the host and counts the
+// results whose bits differ.  Test infrastructure only: it is
 // compiled by the test build and loaded by the GPU tests through ctypes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -18,18 +18,19 @@
 
 namespace {
 
-constexpr int kOut = 6;  // sin, cos of x; of x + d (unchecked); of x + e (checked)
+constexpr int kOut = 8;  // sin, cos of x; of x + d (small tier); of x + e (any); of x + f (mid)
 
-__global__ void trig_kernel(const double* x, const double* d, const double* e, double* out,
-                            int64_t n) {
+__global__ void trig_kernel(const double* x, const double* d, const double* e, const double* f,
+                            double* out, int64_t n) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s, c, r[kOut];
   soax::trig::sincos_fast(x[i], &s, &c);
   r[0] = s;
   r[1] = c;
-  soax::trig::sincos_shift<false>(x[i], s, c, d[i], &r[2], &r[3]);
-  soax::trig::sincos_shift<true>(x[i], s, c, e[i], &r[4], &r[5]);
+  soax::trig::sincos_shift<soax::trig::kTierSmall>(x[i], s, c, d[i], &r[2], &r[3]);
+  soax::trig::sincos_shift<soax::trig::kTierAny>(x[i], s, c, e[i], &r[4], &r[5]);
+  soax::trig::sincos_shift<soax::trig::kTierMid>(x[i], s, c, f[i], &r[6], &r[7]);
   for (int k = 0; k < kOut; ++k) out[i * kOut + k] = r[k];
 }
 
@@ -46,14 +47,16 @@ double uniform(uint64_t* st) {
 }  // namespace
 
 // n arguments x uniform in [lo, hi) (the first 12 replaced by quadrant
-// boundaries and special points inside the range), unchecked shifts d uniform
-// in [-1/64, 1/64], checked shifts e uniform in [-emax, emax].  mismatch[k]
+// boundaries and special points inside the range), small-tier shifts d
+// uniform in [-1/64, 1/64], any-tier shifts e uniform in [-emax, emax],
+// mid-tier shifts f uniform in [-m, m] with m = min(emax, 1/8).  mismatch[k]
 // counts results of kind k (see kOut) whose bits differ between the GPU and
 // the host; first_x[k] is the first such argument.  Returns a hipError_t code.
 extern "C" int trig_device_check(int64_t n, double lo, double hi, double emax, uint64_t seed,
                                  int64_t* mismatch, double* first_x) {
   if (n <= 0) return hipErrorInvalidValue;
-  std::vector<double> x(n), d(n), e(n), got(n * kOut);
+  std::vector<double> x(n), d(n), e(n), f(n), got(n * kOut);
+  const double fmax = emax < soax::trig::kShiftLong ? emax : soax::trig::kShiftLong;
   uint64_t st = seed;
   const double special[12] = {0.0, -0.0, 1e-300, 0.7853981633974483, 1.5707963267948966,
                               3.141592653589793, 4.71238898038469, 6.283185307179586,
@@ -63,19 +66,22 @@ extern "C" int trig_device_check(int64_t n, double lo, double hi, double emax, u
     if (i < 12 && special[i] >= lo && special[i] < hi) x[i] = special[i];
     d[i] = (2.0 * uniform(&st) - 1.0) * soax::trig::kShiftMax;
     e[i] = (2.0 * uniform(&st) - 1.0) * emax;
+    f[i] = (2.0 * uniform(&st) - 1.0) * fmax;
   }
-  double *dx = nullptr, *dd = nullptr, *de = nullptr, *dout = nullptr;
+  double *dx = nullptr, *dd = nullptr, *de = nullptr, *df = nullptr, *dout = nullptr;
   hipError_t err = hipSuccess;
   const size_t bytes = sizeof(double) * n;
   if ((err = hipMalloc(&dx, bytes)) != hipSuccess) goto done;
   if ((err = hipMalloc(&dd, bytes)) != hipSuccess) goto done;
   if ((err = hipMalloc(&de, bytes)) != hipSuccess) goto done;
+  if ((err = hipMalloc(&df, bytes)) != hipSuccess) goto done;
   if ((err = hipMalloc(&dout, bytes * kOut)) != hipSuccess) goto done;
   if ((err = hipMemcpy(dx, x.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess) goto done;
   if ((err = hipMemcpy(dd, d.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess) goto done;
   if ((err = hipMemcpy(de, e.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess) goto done;
+  if ((err = hipMemcpy(df, f.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess) goto done;
   hipLaunchKernelGGL(trig_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, 0,
-                     dx, dd, de, dout, n);
+                     dx, dd, de, df, dout, n);
   if ((err = hipGetLastError()) != hipSuccess) goto done;
   if ((err = hipMemcpy(got.data(), dout, bytes * kOut, hipMemcpyDeviceToHost)) != hipSuccess)
     goto done;
@@ -88,8 +94,9 @@ extern "C" int trig_device_check(int64_t n, double lo, double hi, double emax, u
     soax::trig::sincos_fast(x[i], &s, &c);
     r[0] = s;
     r[1] = c;
-    soax::trig::sincos_shift<false>(x[i], s, c, d[i], &r[2], &r[3]);
-    soax::trig::sincos_shift<true>(x[i], s, c, e[i], &r[4], &r[5]);
+    soax::trig::sincos_shift<soax::trig::kTierSmall>(x[i], s, c, d[i], &r[2], &r[3]);
+    soax::trig::sincos_shift<soax::trig::kTierAny>(x[i], s, c, e[i], &r[4], &r[5]);
+    soax::trig::sincos_shift<soax::trig::kTierMid>(x[i], s, c, f[i], &r[6], &r[7]);
     for (int k = 0; k < kOut; ++k)
       if (memcmp(&r[k], &got[i * kOut + k], sizeof(double)) != 0 && mismatch[k]++ == 0)
         first_x[k] = x[i];
@@ -98,6 +105,7 @@ done:
   hipFree(dx);
   hipFree(dd);
   hipFree(de);
+  hipFree(df);
   hipFree(dout);
   return static_cast<int>(err);
 }
