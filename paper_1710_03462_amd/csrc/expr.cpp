@@ -45,6 +45,63 @@ const char* ctype(int32_t t) {
   }
 }
 
+// Buffer-load and -store expressions of one element of type t at element
+// offset `e` of window `w` (a buffer resource over the workgroup's run of the
+// array; see the streaming kernels of the library): nt loads, write-through
+// nt stores (sc0 sc1 nt).
+const char* win_load(int32_t t) {
+  switch (t) {
+    case kI8: return "(double)(signed char)__builtin_amdgcn_raw_buffer_load_b8(%s, %s, 0, 2)";
+    case kU8: return "(double)__builtin_amdgcn_raw_buffer_load_b8(%s, %s, 0, 2)";
+    case kI32: return "(double)(int)__builtin_amdgcn_raw_buffer_load_b32(%s, (%s) * 4, 0, 2)";
+    case kI64:
+      return "(double)__builtin_bit_cast(long long, __builtin_amdgcn_raw_buffer_load_b64(%s, (%s) * 8, 0, 2))";
+    case kF32:
+      return "(double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(%s, (%s) * 4, 0, 2))";
+    default:
+      return "__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(%s, (%s) * 8, 0, 2))";
+  }
+}
+
+std::string win_store(int32_t t, const std::string& value, const char* w, const char* e) {
+  char buf[1024];
+  switch (t) {
+    case kI8:
+    case kU8:
+      snprintf(buf, sizeof buf, "  __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(%s)(%s), %s, %s, 0, 19);\n",
+               ctype(t), value.c_str(), w, e);
+      break;
+    case kI32:
+      snprintf(buf, sizeof buf, "  __builtin_amdgcn_raw_buffer_store_b32((unsigned)(int)(%s), %s, (%s) * 4, 0, 19);\n",
+               value.c_str(), w, e);
+      break;
+    case kF32:
+      snprintf(buf, sizeof buf,
+               "  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)(%s)), %s, (%s) * 4, 0, 19);\n",
+               value.c_str(), w, e);
+      break;
+    case kI64:
+      snprintf(buf, sizeof buf,
+               "  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, (long long)(%s)), %s, (%s) * 8, 0, 19);\n",
+               value.c_str(), w, e);
+      break;
+    default:
+      snprintf(buf, sizeof buf,
+               "  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, (double)(%s)), %s, (%s) * 8, 0, 19);\n",
+               value.c_str(), w, e);
+      break;
+  }
+  return buf;
+}
+
+int elem_size(int32_t t) {
+  switch (t) {
+    case kI8: case kU8: return 1;
+    case kI32: case kF32: return 4;
+    default: return 8;
+  }
+}
+
 // Each thread evaluates two elements a block-width apart: both elements'
 // loads, then both elements' arithmetic, then both stores.  A thread alone
 // reads and writes its two elements, so a destination that is also a source
@@ -59,7 +116,8 @@ constexpr int kExprPerThread = 2;
 // in the order the source refers to them.
 std::string generate(const ExprPlan& p, std::vector<double>* consts) {
   std::string s;
-  char buf[256];
+  char buf[1024];
+  s += "typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));\n";
   s += "struct Args { const void* src[" + std::to_string(kExprMaxSrc) +
        "]; void* dst; long long n; double c[" + std::to_string(kExprMaxConst) + "]; };\n";
   s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(kExprBlock) +
@@ -73,18 +131,43 @@ std::string generate(const ExprPlan& p, std::vector<double>* consts) {
   std::vector<bool> used(kExprMaxSrc, false);
   for (int k = 0; k < p.nops; ++k)
     if (p.ops[k].op == kOpArray) used[p.ops[k].arg] = true;
+  if (p.stream) {
+    // the workgroup's run of every array, and each element's offset in it
+    s += "  const long long first = (long long)blockIdx.x * " +
+         std::to_string(kExprBlock * kExprPerThread) + ";\n";
+    s += "  const long long cnt = a.n - first < " + std::to_string(kExprBlock * kExprPerThread) +
+         " ? a.n - first : " + std::to_string(kExprBlock * kExprPerThread) + ";\n";
+    s += "  const int e0 = (int)(i0 - first), e1 = (int)(j1 - first);\n";
+    for (int j = 0; j < p.nsrc; ++j) {
+      if (!used[j]) continue;
+      const int es = elem_size(p.src_t[j]);
+      snprintf(buf, sizeof buf,
+               "  const __amdgpu_buffer_rsrc_t w%d = __builtin_amdgcn_make_buffer_rsrc("
+               "(char*)a.src[%d] + first * %d, 0, (int)(cnt * %d), 0x00020000);\n",
+               j, j, es, es);
+      s += buf;
+    }
+    const int es = elem_size(p.dst_t);
+    snprintf(buf, sizeof buf,
+             "  const __amdgpu_buffer_rsrc_t wd = __builtin_amdgcn_make_buffer_rsrc("
+             "(char*)a.dst + first * %d, 0, (int)(cnt * %d), 0x00020000);\n",
+             es, es);
+    s += buf;
+  }
   for (int e = 0; e < kExprPerThread; ++e)
     for (int j = 0; j < p.nsrc; ++j) {
       if (!used[j]) continue;
       const char* t = ctype(p.src_t[j]);
       const char* idx = e == 0 ? "i0" : "j1";
-      if (p.stream)
-        snprintf(buf, sizeof buf,
-                 "  const double s%d_%d = (double)__builtin_nontemporal_load((const %s*)a.src[%d] + %s);\n",
-                 j, e, t, j, idx);
-      else
+      if (p.stream) {
+        char w[8], load[512];
+        snprintf(w, sizeof w, "w%d", j);
+        snprintf(load, sizeof load, win_load(p.src_t[j]), w, e == 0 ? "e0" : "e1");
+        snprintf(buf, sizeof buf, "  const double s%d_%d = %s;\n", j, e, load);
+      } else {
         snprintf(buf, sizeof buf, "  const double s%d_%d = (double)((const %s*)a.src[%d])[%s];\n", j, e, t,
                  j, idx);
+      }
       s += buf;
     }
   // constant k of the program is a.c[cidx[k]]
@@ -140,12 +223,12 @@ std::string generate(const ExprPlan& p, std::vector<double>* consts) {
                                              "has1 ? " + result[1] + " : " + result[0]};
   for (int el = 0; el < kExprPerThread; ++el) {
     const char* idx = el == 0 ? "i0" : "j1";
-    if (p.stream)
-      snprintf(buf, sizeof buf, "  __builtin_nontemporal_store((%s)(%s), (%s*)a.dst + %s);\n", dt,
-               value[el].c_str(), dt, idx);
-    else
+    if (p.stream) {
+      s += win_store(p.dst_t, value[el], "wd", el == 0 ? "e0" : "e1");
+    } else {
       snprintf(buf, sizeof buf, "  ((%s*)a.dst)[%s] = (%s)(%s);\n", dt, idx, dt, value[el].c_str());
-    s += buf;
+      s += buf;
+    }
   }
   s += "}\n";
   return s;

@@ -500,11 +500,6 @@ __global__ __launch_bounds__(256) void soa_to_aos_kernel(const XposeArgs* __rest
 
 // ------------------------------------------------------------ AoSoA tiles
 
-// Element i of the array at offset `off` inside each tile.
-template <typename T>
-__device__ __forceinline__ T* tile_elem(char* base, int64_t tile_bytes, int32_t off, int64_t i) {
-  return reinterpret_cast<T*>(base + (i / kAosoaW) * tile_bytes + off) + (i % kAosoaW);
-}
 
 // SoA <-> AoSoA for arrays order[b..e) (element type T): lane `lane` of
 // `tile` is particle i.  Lanes past n (the last tile's padding) are written
@@ -579,41 +574,69 @@ __global__ __launch_bounds__(256) void aosoa_chunk_kernel(const XposeArgs* __res
   else *tile_p = *soa_p;
 }
 
+// Element `lane` of the tile array at byte `off` of tile base `tb`.  STREAM:
+// through a buffer window over the tile's 64 elements with the streaming
+// cache policies; otherwise a plain global access.
+template <bool STREAM, typename T>
+__device__ __forceinline__ T tile_ld(char* tb, int32_t off, int lane) {
+  const T* arr = reinterpret_cast<const T*>(tb + off);
+  if constexpr (STREAM) return win_ld1(window(arr, 0, kAosoaW), lane);
+  else return arr[lane];
+}
+
+template <bool STREAM, typename T>
+__device__ __forceinline__ void tile_st(char* tb, int32_t off, int lane, T v) {
+  T* arr = reinterpret_cast<T*>(tb + off);
+  if constexpr (STREAM) win_st1(window(arr, 0, kAosoaW), lane, v);
+  else arr[lane] = v;
+}
+
 template <int INTEG, typename PT, typename VT, int TIER, bool STREAM>
 __global__ __launch_bounds__(1024) void aosoa_step_kernel(AosoaStepArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const Abc p = to_abc(a.abc);
-  PT* P[3];
-  VT* V[3];
-  VT* G[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    P[d] = tile_elem<PT>(a.base, a.tile_bytes, a.off_pos[d], i);
-    V[d] = tile_elem<VT>(a.base, a.tile_bytes, a.off_vel[d], i);
-    G[d] = tile_elem<VT>(a.base, a.tile_bytes, a.off_acc[d], i);
-  }
-  if constexpr (!field_integrator(INTEG)) {
-    // one component at a time, as in the SoA kernel
+  // a workgroup is whole waves (the host launches multiples of 64 threads)
+  // and a tile is 64 particles, so every lane of a wave is in the same tile
+  const int64_t tile = __builtin_amdgcn_readfirstlane(static_cast<int>(i / kAosoaW));
+  const int lane = static_cast<int>(i - tile * kAosoaW);
+  char* tb = a.base + tile * a.tile_bytes;
+  if constexpr (!field_integrator(INTEG) && STREAM) {
+    // one component at a time, as in the streaming SoA kernel
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      PT x = ld1<false>(P[d]);
-      VT v = ld1<STREAM && INTEG == kEuler>(V[d]);
-      const VT g = uses_acc(INTEG) ? ld1<STREAM>(G[d]) : VT(0);
+      PT x = tile_ld<true, PT>(tb, a.off_pos[d], lane);
+      VT v = tile_ld<true, VT>(tb, a.off_vel[d], lane);
+      const VT g = uses_acc(INTEG) ? tile_ld<true, VT>(tb, a.off_acc[d], lane) : VT(0);
       euler_component<INTEG, PT, VT>(x, v, g, a.dt, a.wrap);
-      st1<STREAM>(P[d], x);
-      if constexpr (uses_acc(INTEG)) st1<STREAM>(V[d], v);
+      tile_st<true>(tb, a.off_pos[d], lane, x);
+      if constexpr (uses_acc(INTEG)) tile_st<true>(tb, a.off_vel[d], lane, v);
     }
   } else {
-    PT x = ld1<false>(P[0]), y = ld1<false>(P[1]), z = ld1<false>(P[2]);
-    VT u = VT(0), v = VT(0), w = VT(0);
-    update_particle<INTEG, PT, VT, TIER>(x, y, z, u, v, w, VT(0), VT(0), VT(0), a.dt, p, a.wrap);
-    st1<STREAM>(P[0], x);
-    st1<STREAM>(P[1], y);
-    st1<STREAM>(P[2], z);
-    st1<STREAM>(V[0], u);
-    st1<STREAM>(V[1], v);
-    st1<STREAM>(V[2], w);
+    // every load before the first store (cache-resident sets are bound by
+    // latency; see the SoA kernel)
+    PT x = tile_ld<STREAM, PT>(tb, a.off_pos[0], lane), y = tile_ld<STREAM, PT>(tb, a.off_pos[1], lane),
+       z = tile_ld<STREAM, PT>(tb, a.off_pos[2], lane);
+    VT u = VT(0), v = VT(0), w = VT(0), g0 = VT(0), g1 = VT(0), g2 = VT(0);
+    if constexpr (!field_integrator(INTEG)) {
+      u = tile_ld<STREAM, VT>(tb, a.off_vel[0], lane);
+      v = tile_ld<STREAM, VT>(tb, a.off_vel[1], lane);
+      w = tile_ld<STREAM, VT>(tb, a.off_vel[2], lane);
+    }
+    if constexpr (uses_acc(INTEG)) {
+      g0 = tile_ld<STREAM, VT>(tb, a.off_acc[0], lane);
+      g1 = tile_ld<STREAM, VT>(tb, a.off_acc[1], lane);
+      g2 = tile_ld<STREAM, VT>(tb, a.off_acc[2], lane);
+    }
+    update_particle<INTEG, PT, VT, TIER>(x, y, z, u, v, w, g0, g1, g2, a.dt, p, a.wrap);
+    tile_st<STREAM>(tb, a.off_pos[0], lane, x);
+    tile_st<STREAM>(tb, a.off_pos[1], lane, y);
+    tile_st<STREAM>(tb, a.off_pos[2], lane, z);
+    if constexpr (INTEG != kEuler) {
+      tile_st<STREAM>(tb, a.off_vel[0], lane, u);
+      tile_st<STREAM>(tb, a.off_vel[1], lane, v);
+      tile_st<STREAM>(tb, a.off_vel[2], lane, w);
+    }
   }
 }
 

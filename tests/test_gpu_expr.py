@@ -2,7 +2,7 @@
 element-by-element evaluation (Section 4.1's whole-array expressions):
 bit-exact for every op (each is one correctly rounded double operation on
 both sides), on set arrays and plain tensors, at ragged sizes, in place,
-and at a size that takes the streaming (nontemporal) kernel."""
+and at sizes that take the streaming kernel."""
 import numpy as np
 import pytest
 import torch
@@ -91,6 +91,25 @@ def test_programs_on_tensors(name, dst_t, n):
     assert bits_equal(dst.cpu().numpy(), want)
 
 
+@pytest.mark.parametrize("name", list(PROGRAMS))
+@pytest.mark.parametrize("dst_t", [np.float32, np.float64])
+def test_programs_on_tensors_streaming_size(name, dst_t):
+    # every source type at a footprint above 128 MB (5e6 x 30-34 bytes): the
+    # kernel that moves each element through buffer windows
+    n = 5_000_003
+    host = make_sources(n, 11)
+    dev = [torch.from_numpy(h).cuda() for h in host]
+    leaves = [E.array(t) for t in dev]
+    ex = PROGRAMS[name](*leaves)
+    dst = torch.empty(n, dtype=torch.float32 if dst_t == np.float32 else torch.float64, device="cuda")
+    soax.evaluate(dst, ex)
+    torch.cuda.synchronize()
+    keys = ex.keys()
+    want = ref.eval_program([host[next(j for j, t in enumerate(dev) if t is k)] for k in keys],
+                            to_ops(ex, keys), dst_t)
+    assert bits_equal(dst.cpu().numpy(), want)
+
+
 def test_in_place_update_and_repeat():
     n = 10_007
     x = torch.linspace(-3, 3, n, dtype=torch.float64, device="cuda")
@@ -107,7 +126,7 @@ def test_in_place_update_and_repeat():
 
 
 def test_streaming_size_sampled():
-    # 1.2e7 doubles x 3 arrays > 128 MB: the nontemporal kernel
+    # 1.2e7 doubles x 3 arrays > 128 MB: the streaming kernel
     n = 12_000_001
     g = torch.Generator(device="cuda")
     g.manual_seed(0)
