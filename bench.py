@@ -794,7 +794,7 @@ def main():
     per_launch = t.ms / (args.steps * nsteps)
     log(f"[bench] SoA RK2: {value:.4e} updates/s, {per_launch:.3f} ms/launch")
 
-    kname = "soa_step_kernel<RK2_ABC,double,float,1>"
+    kname = "soa_step_kernel<RK2_ABC,double,float,2>"
     traffic = traffic_from_profiles(kname, "hbm_bytes_per_launch")
     roofline = {"kernel": kname, "bound": "hbm", "achieved": gbs(60 * n, per_launch),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -187,8 +187,9 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
  * Override the launch shape of soax_step for one layout: block threads
  * (64..1024, multiple of 64) and particles per thread (1, 2 or 4; SoA only).
  * 0 restores the default: 128 threads (256 for the AoS layouts), one particle
- * per thread, two for SOAX_RK2_ABC steps of SoA arrays that are 16-byte
- * aligned.  Results do not depend on the shape.
+ * per thread, two for the steps in the ABC field (RK2, Heun, RK4) on SoA
+ * arrays that are 16-byte aligned.  Heun and RK4 steps take at most two per
+ * thread.  Results do not depend on the shape.
  */
 soax_status soax_step_config(soax_set* set, int32_t layout, int32_t block, int32_t per_thread);
 
@@ -492,15 +493,18 @@ soax_status soax_batch_tune(soax_batch* batch, const char* cache_path);
 /* ------------------------------------------------------------ utilities */
 
 /* dst[0..bytes) = src[0..bytes) with 16-byte loads/stores (16-byte aligned
- * pointers): the bandwidth probe the step kernels are measured against. */
+ * pointers) through the streaming cache policies of the step kernels: the
+ * bandwidth probe the step kernels are measured against. */
 soax_status soax_copy(void* dst, const void* src, int64_t bytes, void* stream);
 
 /*
  * Bandwidth probes: the memory accesses of the streaming SoA steps with their
  * arithmetic taken out, on caller-owned device arrays pos[3] (n doubles each)
- * and vel[3] (n floats each), one particle per thread with the step kernels'
- * loads, stores and cache hints.  They bound what the step kernels can reach
- * on this memory system, as soax_copy bounds plain streaming:
+ * and vel[3] (n floats each), one particle per thread (the RK2 step itself
+ * takes two), with the step kernels' buffer windows and cache policies (nt
+ * loads, sc0 sc1 nt stores).  They measure what the step kernels' access
+ * patterns reach on this memory system, as soax_copy does for plain
+ * streaming:
  *   SOAX_PROBE_RK2    read pos, write pos (unchanged) and vel = (float)pos:
  *                     the 60 B per particle of an RK2, Heun or RK4 step;
  *   SOAX_PROBE_EULER  per component read pos and vel, write pos (unchanged

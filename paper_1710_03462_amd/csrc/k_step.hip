@@ -165,9 +165,13 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
 template <int INTEG, typename PT, typename VT, int TIER, bool STREAM>
 hipError_t soa_step_launch(int vec, int64_t grid, int block, const SoaStepArgs& a, hipStream_t s) {
   if constexpr (INTEG == kHeunAbc || INTEG == kRk4Abc) {
-    // one particle per thread only (the host forces vec = 1 for these)
-    hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 1, TIER, STREAM>), dim3(grid), dim3(block),
-                       0, s, a);
+    // one or two particles per thread (the host caps vec at 2 for these)
+    if (vec == 1)
+      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 1, TIER, STREAM>), dim3(grid),
+                         dim3(block), 0, s, a);
+    else
+      hipLaunchKernelGGL((soa_step_kernel<INTEG, PT, VT, 2, TIER, STREAM>), dim3(grid),
+                         dim3(block), 0, s, a);
     return hipGetLastError();
   }
   switch (vec) {
@@ -196,7 +200,7 @@ hipError_t soa_step_stream(bool stream, int vec, int64_t grid, int block, const 
 
 template <int INTEG, typename PT, typename VT>
 hipError_t soa_step_vec(int vec, int block, const SoaStepArgs& a, hipStream_t s) {
-  if constexpr (INTEG == kHeunAbc || INTEG == kRk4Abc) vec = 1;
+  if constexpr (INTEG == kHeunAbc || INTEG == kRk4Abc) vec = vec > 2 ? 2 : vec;
   const int64_t threads = (a.n + vec - 1) / vec;
   const int64_t grid = (threads + block - 1) / block;
   if (grid == 0) return hipSuccess;

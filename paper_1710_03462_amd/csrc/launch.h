@@ -51,11 +51,13 @@ inline __host__ __device__ bool small_steps(double dt, double A, double B, doubl
 
 // What the host proves about every displacement of a step of the field
 // integrators (the shift of the angle additions): kTierSmall, every shift at
-// most kShiftLimit; kTierMid, every shift at most 1/8 (the longer series of
-// the angle addition, checked against kShiftMidLimit, 1/8 less 2^-20 of it,
-// so that no rounding of dt u can carry a shift past 1/8); kTierAny, no
-// bound.  A kernel instantiated for a tier gives exactly the results of the
-// kTierAny kernel on every step that satisfies the tier's bound.
+// most kShiftLimit (the short series); kTierMid, every shift at most 1/8 (the
+// longer series; checked against kShiftMidLimit, 1/8 less 2^-20 of it, so
+// that no rounding of dt u can carry a shift past 1/8); kTierAny, no bound.
+// The tier is a function of dt and the amplitudes alone, so every layout, the
+// batch and the single-set kernels take the same one for the same step; the
+// mid-tier kernels give exactly the results of the kTierAny kernels on every
+// step that satisfies their bound.
 enum ShiftTier : int32_t { kTierSmall = 0, kTierMid = 1, kTierAny = 2 };
 constexpr double kShiftMidLimit = 0.125 * (1.0 - 0x1p-20);
 

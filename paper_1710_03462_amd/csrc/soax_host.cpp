@@ -225,10 +225,10 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
     a.abc = abc;
     a.wrap = wrap;
     // workgroups of 128; one particle per thread, except two consecutive
-    // particles (16-byte position accesses) for the RK2 step: the fastest
-    // shapes measured on the MI355X at 1e8 particles (RK2 3% faster with two
-    // than with one; Euler 10% slower)
-    int vec = set->vec ? set->vec : (integrator == SOAX_RK2_ABC ? 2 : 1);
+    // particles (16-byte position accesses) for the field integrators: the
+    // fastest shapes measured on the MI355X at 1e8 particles (RK2 and Heun
+    // 3% faster with two than with one, RK4 2%; Euler 10% slower)
+    int vec = set->vec ? set->vec : (field_integrator(integrator) ? 2 : 1);
     if (!set->soa_vec_ok) vec = 1;
     const int block = set->block[SOAX_SOA] ? set->block[SOAX_SOA] : 128;
     for (int64_t k = 0; k < nsteps; ++k)

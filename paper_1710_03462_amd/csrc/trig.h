@@ -20,10 +20,11 @@
 // their Taylor series (truncated after d^5 and d^6; omitted terms below
 // 5e-17 absolute).  A time step moves a particle by dt*u, far less than 1/64
 // for the step sizes of interest, so the midpoint and end-point values of a
-// step come from the start-point values without a second reduction.  The
-// checked form also takes shifts up to 1/8, with series truncated after d^9
-// and d^10; larger shifts fall back to sincos_fast(x + d).  The shift uses the exact sum x + d, which differs from
-// the rounded sum by at most half an ulp of x.
+// step come from the start-point values without a second reduction.  Where
+// shifts may exceed 1/64 the longer series (truncated after d^9 and d^10)
+// take every shift up to 1/8, and larger shifts fall back to
+// sincos_fast(x + d) (see the tiers below).  The shift uses the exact sum
+// x + d, which differs from the rounded sum by at most half an ulp of x.
 //
 // Measured on the host against glibc over seeded arguments: within 2 ulp for
 // |x| up to 2^19 (the 2-ulp cases at large |x|, where the reduction's error
@@ -133,7 +134,7 @@ __host__ __device__ __forceinline__ void sincos_fast(double x, double* s, double
 constexpr double T1 = -inv_fact(3), T2 = inv_fact(5);
 // cos d - 1 = w (-1/2 + w (U1 + w U2))
 constexpr double U1 = inv_fact(4), U2 = -inv_fact(6);
-// the longer series of the checked form for 1/64 < |d| <= 1/8:
+// the longer series, for |d| <= 1/8:
 // sin d = d + d^3 (T1 + w (T2 + w (T3 + w T4))), omitted terms below 3e-18;
 // cos d - 1 = w (-1/2 + w (U1 + w (U2 + w (U3 + w U4)))), below 3e-20
 constexpr double kShiftLong = 1.0 / 8;
@@ -141,11 +142,11 @@ constexpr double T3 = -inv_fact(7), T4 = inv_fact(9);
 constexpr double U3 = inv_fact(8), U4 = -inv_fact(10);
 
 // What the caller guarantees about the shift, by tier.  kTierSmall:
-// |d| <= kShiftMax (the short series alone).  kTierMid: |d| <= kShiftLong
-// (per lane, the short series up to kShiftMax and the longer one beyond).
-// kTierAny: any d (as kTierMid, and a full reduction of x + d beyond
-// kShiftLong).  Where its guarantee holds, each tier gives exactly the
-// results of kTierAny.
+// |d| <= kShiftMax; the short series.  kTierMid: |d| <= kShiftLong; the
+// longer series for every shift (no branch, so the lanes of a wave never
+// split between two series).  kTierAny: any d; the longer series up to
+// kShiftLong and a full reduction of x + d beyond it.  Where its guarantee
+// holds, kTierMid gives exactly the results of kTierAny.
 constexpr int kTierSmall = 0;
 constexpr int kTierMid = 1;
 constexpr int kTierAny = 2;
@@ -155,16 +156,16 @@ __host__ __device__ __forceinline__ void sincos_shift(double x, double sx, doubl
                                                       double* s, double* c) {
   double sd, cm1;
   const double w = d * d;
-  if (TIER != kTierSmall && !(fabs(d) <= kShiftMax)) {
+  if (TIER == kTierSmall) {
+    sd = fma(d * w, fma(w, T2, T1), d);
+    cm1 = w * fma(w, fma(w, U2, U1), -0.5);
+  } else {
     if (TIER == kTierAny && !(fabs(d) <= kShiftLong)) {
       sincos_fast(x + d, s, c);
       return;
     }
     sd = fma(d * w, fma(w, fma(w, fma(w, T4, T3), T2), T1), d);
     cm1 = w * fma(w, fma(w, fma(w, fma(w, U4, U3), U2), U1), -0.5);
-  } else {
-    sd = fma(d * w, fma(w, T2, T1), d);
-    cm1 = w * fma(w, fma(w, U2, U1), -0.5);
   }
   // sin(x+d) = sin x + (sin x (cos d - 1) + cos x sin d), likewise for cos
   *s = fma(cx, sd, fma(sx, cm1, sx));

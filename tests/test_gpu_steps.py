@@ -351,6 +351,29 @@ def test_field_integrators_large_steps_and_f64_velocity(ref, integ):
             assert np.abs(got[4 + d] - want[4 + d]).max() <= 1e-12
 
 
+@pytest.mark.parametrize("integ", ["rk2_abc", "heun_abc", "rk4_abc"])
+@pytest.mark.parametrize("scale", [0.02 * 3, 0.125 * (1 - 2.0 ** -19), 0.125 * (1 + 2.0 ** -19)])
+def test_field_integrators_around_the_mid_tier_bound(ref, integ, scale):
+    # dt (|A|+|B|+|C|) = scale: 0.06 and just inside 1/8 take the mid tier
+    # (short or long angle-addition series per lane, no range check beyond
+    # 1/8); just above 1/8 the unbounded tier.  Every layout runs the same
+    # tier, so SoA and AoS also agree bit for bit.
+    fields = si.BASE_FIELDS
+    arrays = si.random_state(fields, 2053, 91)
+    abc = [1.0, 1.0, 1.0]
+    dt = scale / 3.0
+    want = run_ref(ref, fields, arrays, getattr(ref, integ.upper()), dt, 4, abc=abc)
+    got = {}
+    for layout in LAYOUTS:
+        got[layout] = run_gpu(fields, arrays, layout, integ, dt, 4, abc=abc)
+        for d in range(3):
+            assert_positions_close(got[layout][1 + d], want[1 + d])
+            assert_fields_close(got[layout][4 + d], want[4 + d])
+    for layout in LAYOUTS:
+        for a, b in zip(got[layout], got["soa"]):
+            assert np.array_equal(a, b), layout
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("packed", [False, True])
 def test_symplectic_euler_bit_exact(ref, layout, packed):

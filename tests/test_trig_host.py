@@ -37,21 +37,30 @@ def test_sincos_within_two_ulp_of_glibc(exe, lo, hi):
 
 @pytest.mark.parametrize("lo,hi", [(-1.0, 8.0), (-20.0, 20.0), (-1e-3, 1e-3)])
 def test_checked_shift_longer_series_within_one_ulp(exe, lo, hi):
-    # shifts up to 1/8: the checked form's degree-9/10 series keeps the
-    # absolute error of sin/cos(x + d) within one ulp of 1
+    # shifts up to 1/8: the degree-9/10 series of the mid and unbounded tiers
+    # keeps the absolute error of sin/cos(x + d) within one ulp of 1
     out = subprocess.run([exe, str(lo), str(hi), "400000", str(1.0 / 8)], check=True,
                          capture_output=True, text=True).stdout.split()
     assert float(out[4]) <= 1.0 and float(out[5]) <= 1.0, out
 
 
 @pytest.mark.parametrize("shift_max", [1.0 / 64, 1.0 / 8, 0.5])
-def test_shift_tiers_equal_the_any_tier_inside_their_bounds(exe, shift_max):
-    # kTierSmall (|d| <= 1/64) and kTierMid (|d| <= 1/8) drop the range checks
-    # the host has proven unneeded; inside those bounds they must give the
-    # any-tier results bit for bit (last field: count of differing pairs)
+def test_mid_tier_equals_the_any_tier_inside_its_bound(exe, shift_max):
+    # kTierMid (|d| <= 1/8) drops the range check the host has proven
+    # unneeded; inside that bound it must give the any-tier results bit for
+    # bit (field 6: count of differing pairs)
     out = subprocess.run([exe, "-20", "20", "400000", str(shift_max)], check=True,
                          capture_output=True, text=True).stdout.split()
     assert int(out[6]) == 0, out
+
+
+@pytest.mark.parametrize("lo,hi", [(-1.0, 8.0), (-20.0, 20.0), (-1e-3, 1e-3)])
+def test_small_tier_short_series_within_one_ulp(exe, lo, hi):
+    # kTierSmall's degree-5/6 series for |d| <= 1/64 (field 7: its largest
+    # absolute error in units of ulp(1) against long double)
+    out = subprocess.run([exe, str(lo), str(hi), "400000", str(1.0 / 64)], check=True,
+                         capture_output=True, text=True).stdout.split()
+    assert float(out[7]) <= 1.0, out
 
 
 @pytest.mark.parametrize("lo,hi", [(-1.0, 8.0), (-20.0, 20.0)])
