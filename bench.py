@@ -671,25 +671,53 @@ def sweep_markdown(rows):
             l1 = f"{1 - miss / c['TCP_TOTAL_CACHE_ACCESSES_sum']:.2f}"
         return l1, l2
 
-    lines = ["| SIZE | N | SoA µs | AoS µs | naive µs | SoA ns/p | AoS/SoA | naive/SoA | "
-             "L1 hit soa/aos/naive | L2 hit soa/aos/naive |",
-             "|---|---|---|---|---|---|---|---|---|---|"]
+    def traffic(v, n):
+        # bytes past the L2 per particle-step, FETCH_SIZE and WRITE_SIZE (KiB
+        # per dispatch) scaled by the copy-kernel calibration of the committed
+        # counter data (FETCH_SIZE counts half the bytes on this GPU)
+        c = v.get("counters_per_launch", {})
+        if "FETCH_SIZE" not in c and "WRITE_SIZE" not in c:
+            return ""
+        try:
+            with open(PROFILE_TRAFFIC) as f:
+                cal = json.load(f)["calibration"]
+        except (OSError, ValueError, KeyError):
+            cal = {"read_factor": 1.0, "write_factor": 1.0}
+        rd = c.get("FETCH_SIZE", 0.0) * 1024 * cal["read_factor"] / n
+        wr = c.get("WRITE_SIZE", 0.0) * 1024 * cal["write_factor"] / n
+        return f"{rd:.1f}+{wr:.1f}"
+
+    with_traffic = any("FETCH_SIZE" in r.get(lay, {}).get("counters_per_launch", {})
+                       or "WRITE_SIZE" in r.get(lay, {}).get("counters_per_launch", {})
+                       for r in rows for lay in SWEEP_LAYOUTS)
+    head = ("| SIZE | N | SoA µs | AoS µs | naive µs | SoA ns/p | AoS/SoA | naive/SoA | "
+            "L1 hit soa/aos/naive | L2 hit soa/aos/naive |")
+    rule = "|---|---|---|---|---|---|---|---|---|---|"
+    if with_traffic:
+        head += " read+write B/particle soa / aos / naive |"
+        rule += "---|"
+    lines = [head, rule]
     for r in rows:
         us = [f"{r[lay]['kernel_ns'] / 1e3:.2f}" if "kernel_ns" in r.get(lay, {}) else ""
               for lay in SWEEP_LAYOUTS]
         nsp = f"{r['soa']['ns_per_particle']:.4f}" if "ns_per_particle" in r.get("soa", {}) else ""
         ratio = [f"{r[k]:.2f}" if k in r else "" for k in ("aos_over_soa", "naive_over_soa")]
         h = [hits(r.get(lay, {})) for lay in SWEEP_LAYOUTS]
-        lines.append(f"| {r['SIZE']} | {r['N']:.0e} | {' | '.join(us)} | {nsp} | "
-                     f"{' | '.join(ratio)} | {'/'.join(x[0] for x in h)} | "
-                     f"{'/'.join(x[1] for x in h)} |")
+        line = (f"| {r['SIZE']} | {r['N']:.0e} | {' | '.join(us)} | {nsp} | "
+                f"{' | '.join(ratio)} | {'/'.join(x[0] for x in h)} | "
+                f"{'/'.join(x[1] for x in h)} |")
+        if with_traffic:
+            line += f" {' / '.join(traffic(r.get(lay, {}), r['N']) for lay in SWEEP_LAYOUTS)} |"
+        lines.append(line)
     return "\n".join(lines)
 
 
-def cpu_baseline(ref, si, target_s=20.0):
-    """The oracle's RK2 SoA step on a bounded sample of the headline workload.
-    The sample is sized from a short probe, which overestimates the cost per
-    update about twofold, so the timed run lands near 10 s."""
+def cpu_baseline(ref, si, target_s=14.0):
+    """The oracle's RK2 step on a bounded sample of the headline workload, in
+    SoA (the reported value) and, on half as many particles, in AoS records
+    (the CPU's SoA/AoS ratio beside the GPU's).  The sample is sized from a
+    short probe, which overestimates the cost per update about twofold, so the
+    timed SoA run lands near 7-10 s and the AoS run near half that."""
     sch = ref.Schema(si.BASE_FIELDS)
     cores = ref.threads()
     probe_n, probe_steps = 20000, 5
@@ -702,10 +730,19 @@ def cpu_baseline(ref, si, target_s=20.0):
     t0 = time.perf_counter()
     ref.step_soa(sch, arrays, ref.RK2_ABC, 1e-3, 50, abc=[1, 1, 1], wrap=True)
     el = time.perf_counter() - t0
-    return {"value": n * 50 / el, "unit": "particle-updates/s", "cores": cores, "kind": "oracle",
+    del arrays
+    n_aos = n // 2
+    aos = ref.soa_to_aos(sch, ref.fill(sch, n_aos, seed=0, vel_mode=1, abc=[1, 1, 1]))
+    t0 = time.perf_counter()
+    ref.step_aos(sch, aos, n_aos, ref.RK2_ABC, 1e-3, 50, abc=[1, 1, 1], wrap=True)
+    el_aos = time.perf_counter() - t0
+    soa_rate, aos_rate = n * 50 / el, n_aos * 50 / el_aos
+    return {"value": soa_rate, "unit": "particle-updates/s", "cores": cores, "kind": "oracle",
             "cpu_model": cpu_model(),
+            "aos_value": aos_rate, "soa_over_aos": soa_rate / aos_rate,
             "sample": f"{n} particles x 50 RK2 steps of the same record and field "
-                      f"(SoA, OpenMP static schedule), {el:.1f} s"}
+                      f"(SoA, OpenMP static schedule), {el:.1f} s; AoS records: {n_aos} "
+                      f"particles x 50 steps, {el_aos:.1f} s"}
 
 
 def traffic_from_profiles(kernel, launches_bytes_key):

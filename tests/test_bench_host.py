@@ -109,3 +109,23 @@ def test_sweep_markdown_merges_time_and_counters(tmp_path):
     md = bench.sweep_markdown(rows)
     assert "| 0 | 1e+03 | 4.00 | 6.00 | 8.00 | 4.0000 | 1.50 | 2.00 |" in md
     assert "1.00/1.00/1.00" in md
+
+
+def test_sweep_markdown_traffic_columns(tmp_path):
+    import csv
+
+    import bench
+    sizes, ns, steps = (0,), (1000,), 2
+    launches = _sweep_launches(bench, sizes, ns, steps, lambda size, n, lay: 1)
+    with open(tmp_path / "x_counter_collection.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for i, (name, grid, _) in enumerate(launches):
+            w.writerow([i + 1, grid, name, "WRITE_SIZE", 12.0])  # KiB per dispatch
+    rows = bench.sweep_report_rows([str(tmp_path)], sizes, ns, steps)
+    md = bench.sweep_markdown(rows)
+    assert "read+write B/particle" in md
+    # 12 KiB over 1000 particles with the committed write calibration
+    import json
+    cal = json.load(open(bench.PROFILE_TRAFFIC))["calibration"]["write_factor"]
+    assert f"0.0+{12 * 1024 * cal / 1000:.1f}" in md

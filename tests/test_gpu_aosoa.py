@@ -75,6 +75,41 @@ def test_steps_on_tiles_match_oracle(ref, integ, n):
     ps.close()
 
 
+@pytest.mark.parametrize("integ", EULERS + FIELDS_INTEG)
+def test_steps_on_tiles_streaming_size(ref, integ):
+    # above 128 MB of stepped arrays the tiled step streams through buffer
+    # windows over each wave's tile; a ragged last tile, every particle
+    # against the oracle, and the field steps bit-identical to the SoA kernels
+    n = 4_000_037
+    fields = si.WIDE_FIELDS
+    ps, arrays = make(fields, n, 7)
+    ps.soa_to_aosoa()
+    abc = [1.0, 0.8, 0.6]
+    ps.step("aosoa", integ, 1e-3, 3, abc=abc, wrap=True)
+    ps.aosoa_to_soa()
+    torch.cuda.synchronize()
+    got = ps.download_soa()
+    sch = ref.Schema(fields)
+    want = [a.copy() for a in arrays]
+    ref.step_soa(sch, want, getattr(ref, integ.upper()), 1e-3, 3, abc=abc, wrap=True)
+    pos = set(range(sch.array_index("pos"), sch.array_index("pos") + 3))
+    vel = set(range(sch.array_index("vel"), sch.array_index("vel") + 3))
+    for a, (g, w) in enumerate(zip(got, want)):
+        if integ in FIELDS_INTEG and a in pos:
+            assert_positions_close(g, w)
+        elif integ in FIELDS_INTEG and a in vel:
+            assert_fields_close(g, w)
+        else:
+            assert np.array_equal(g.view(np.uint8), w.view(np.uint8)), a
+    if integ in FIELDS_INTEG:
+        ps.upload_soa(arrays)
+        ps.step("soa", integ, 1e-3, 3, abc=abc, wrap=True)
+        torch.cuda.synchronize()
+        for a, (g, w) in enumerate(zip(got, ps.download_soa())):
+            assert np.array_equal(g.view(np.uint8), w.view(np.uint8)), a
+    ps.close()
+
+
 def test_float_record_on_tiles(ref):
     fields = si.particle_size_fields(8)  # the paper's Particle<8>: float x, v, temp
     ps, arrays = make(fields, 1000, 9)
