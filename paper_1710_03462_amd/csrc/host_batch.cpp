@@ -451,7 +451,7 @@ extern "C" soax_status soax_batch_tune(soax_batch* b, const char* cache_path) {
     *ms_out = ms / reps;
     return SOAX_OK;
   };
-  const int blocks[] = {128, 256, 512};
+  const int blocks[] = {64, 128, 256, 512};
   const int ppts[] = {1, 2, 4};
   // the last candidate gives every tile its own workgroup
   const int bpcs[] = {2, 4, 8, 16, 32, 64, kMaxBlocksPerCu};

@@ -224,13 +224,16 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
     a.dt = dt;
     a.abc = abc;
     a.wrap = wrap;
-    // workgroups of 128; one particle per thread, except two consecutive
-    // particles (16-byte position accesses) for the field integrators: the
-    // fastest shapes measured on the MI355X at 1e8 particles (RK2 and Heun
-    // 3% faster with two than with one, RK4 2%; Euler 10% slower)
+    // one particle per thread in workgroups of 128, except two consecutive
+    // particles (16-byte position accesses) in workgroups of 64 for the field
+    // integrators: the fastest shapes measured on the MI355X at 1e8
+    // particles (two per thread: RK2 and Heun 3% faster than one, RK4 2%,
+    // Euler 10% slower; then 64 threads: RK2 and Heun about 1% faster than
+    // 128 in interleaved runs, RK4 level, Euler 6% slower)
     int vec = set->vec ? set->vec : (field_integrator(integrator) ? 2 : 1);
     if (!set->soa_vec_ok) vec = 1;
-    const int block = set->block[SOAX_SOA] ? set->block[SOAX_SOA] : 128;
+    const int block = set->block[SOAX_SOA] ? set->block[SOAX_SOA]
+                                           : (field_integrator(integrator) ? 64 : 128);
     for (int64_t k = 0; k < nsteps; ++k)
       HIP_TRY(launch_soa_step(integrator, L.f[fp].dtype, L.f[fv].dtype, vec, block, a, s),
               "SoA step launch");

@@ -130,7 +130,7 @@ def test_tuner_keeps_state_and_writes_cache(tmp_path):
     cfg = b.tune(cache)
     after = download(sets)
     assert same(before, after)
-    assert cfg[0] in (128, 256, 512) and cfg[1] in (1, 2, 4) and cfg[2] in (2, 4, 8, 16, 32, 64, 65536)
+    assert cfg[0] in (64, 128, 256, 512) and cfg[1] in (1, 2, 4) and cfg[2] in (2, 4, 8, 16, 32, 64, 65536)
     assert os.path.exists(cache)
     text = open(cache).read()
     assert "batch_rk2" in text and f'"block": {cfg[0]}' in text

@@ -74,3 +74,22 @@ def test_checked_shift_full_reduction_beyond_the_series(exe, lo, hi):
     top = max(abs(lo), abs(hi)) + 0.5
     bound = 1.0 + 0.5 * math.ulp(top) / 2.0 ** -52 + 1.0
     assert float(out[4]) <= bound and float(out[5]) <= bound, (out, bound)
+
+
+@pytest.mark.parametrize("dt,abc,tier", [
+    (1e-3, (1, 1, 1), 0),                       # 3e-3: short series
+    (1.0 / 192, (1, 1, 1), 0),                  # exactly 1/64
+    (1.0 / 192 * (1 + 2.0 ** -40), (1, 1, 1), 1),
+    (0.04, (1, 1, 1), 1),                       # 0.12
+    (0.125 / 3 * (1 - 2.0 ** -19), (1, 1, 1), 1),
+    (0.125 / 3 * (1 - 2.0 ** -22), (1, 1, 1), 2),  # inside 1/8 but within the 2^-20 margin
+    (0.05, (1, 1, 1), 2),
+    (-0.04, (-1, 1, -1), 1),                    # signs do not matter
+    (1e-2, (0, 0, 0), 0),                       # no field
+])
+def test_shift_tier_selection(exe, dt, abc, tier):
+    # the host's proof of the step's shift bound: |dt| (|A|+|B|+|C|) <= 1/64
+    # -> 0, <= 1/8 (1 - 2^-20) -> 1, else 2
+    out = subprocess.run([exe, "tier", repr(dt), *(repr(float(a)) for a in abc)], check=True,
+                         capture_output=True, text=True).stdout.split()
+    assert int(out[0]) == tier, (dt, abc, out)

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include "launch.h"
 #include "trig.h"
 
 static double ulp_of(double v) {
@@ -14,6 +15,11 @@ static double ulp_of(double v) {
 }
 
 int main(int argc, char** argv) {
+  // "tier dt A B C": the shift tier the host selects for a step
+  if (argc == 6 && argv[1][0] == 't') {
+    printf("%d\n", soax::shift_tier(atof(argv[2]), atof(argv[3]), atof(argv[4]), atof(argv[5])));
+    return 0;
+  }
   const double lo = argc > 1 ? atof(argv[1]) : -1.0;
   const double hi = argc > 2 ? atof(argv[2]) : 8.0;
   const long n = argc > 3 ? atol(argv[3]) : 1000000;
