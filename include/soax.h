@@ -189,8 +189,9 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
  * 0 restores the default: 128 threads (256 for the AoS layouts) and one
  * particle per thread; for the steps in the ABC field (RK2, Heun, RK4) on SoA
  * arrays that are 16-byte aligned, 64 threads and two particles per thread.
- * Heun and RK4 steps take at most two per thread.  Results do not depend on
- * the shape.
+ * Heun and RK4 steps, and any step whose positions or velocities are 8-byte
+ * elements, take at most two per thread.  Results do not depend on the
+ * shape.
  */
 soax_status soax_step_config(soax_set* set, int32_t layout, int32_t block, int32_t per_thread);
 
@@ -481,7 +482,7 @@ soax_status soax_batch_get_config(const soax_batch* batch, int32_t* block, int32
 /*
  * Autotune the batch kernel's shape by timing candidate shapes on the
  * batch itself (state saved and restored, so particles do not move) and keep
- * the fastest.  Candidates: block 64/128/256/512, particles per thread 1/2/4,
+ * the fastest.  Candidates: block 64/128/256/512, particles per thread 1/2,
  * workgroups per CU 2/4/8/16/32/64 and 65536 (one tile per workgroup); the
  * four fastest and the shape in use are timed again with longer runs before
  * the choice.  The runs use the dt and amplitudes of the most recent

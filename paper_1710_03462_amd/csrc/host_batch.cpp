@@ -452,7 +452,9 @@ extern "C" soax_status soax_batch_tune(soax_batch* b, const char* cache_path) {
     return SOAX_OK;
   };
   const int blocks[] = {64, 128, 256, 512};
-  const int ppts[] = {1, 2, 4};
+  // four particles per thread splits the 8-byte position runs into
+  // half-coalesced 16-byte accesses (measured 2.5x slower): not a candidate
+  const int ppts[] = {1, 2};
   // the last candidate gives every tile its own workgroup
   const int bpcs[] = {2, 4, 8, 16, 32, 64, kMaxBlocksPerCu};
   const TuneEntry current{b->block, b->per_thread, b->blocks_per_cu, 0.0};

@@ -78,7 +78,8 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
       // per wave in flight instead of six -- faster on HBM for this in-place
       // update.  Cache-resident sets take the path below, whose loads all
       // leave before the first store: there the step is bound by latency,
-      // and three dependent round trips would triple it.
+      // and the component order waits out three round trips in turn (its
+      // kernel took 2.4-2.5 us at 1e3 particles against 2.2 us).
       PT* P[3] = {px, py, pz};
       VT* Vv[3] = {vx, vy, vz};
       const VT* G[3] = {ax, ay, az};
@@ -103,13 +104,9 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
     PT x[VEC], y[VEC], z[VEC];
     VT u[VEC], v[VEC], w[VEC];
     VT ga[VEC], gb[VEC], gc[VEC];
-    // field steps: a wave issuing its loads or stores goes ahead of waves in
-    // their arithmetic, so memory requests leave early (measured ~1% faster)
-    if constexpr (field_integrator(INTEG)) __builtin_amdgcn_s_setprio(3);
     step_ld<STREAM, PT, VEC>(px, first, cnt, e, x);
     step_ld<STREAM, PT, VEC>(py, first, cnt, e, y);
     step_ld<STREAM, PT, VEC>(pz, first, cnt, e, z);
-    if constexpr (field_integrator(INTEG)) __builtin_amdgcn_s_setprio(0);
     if constexpr (kReadsVel) {
       step_ld<STREAM, VT, VEC>(vx, first, cnt, e, u);
       step_ld<STREAM, VT, VEC>(vy, first, cnt, e, v);
@@ -129,7 +126,6 @@ __global__ __launch_bounds__(1024) void soa_step_kernel(SoaStepArgs a) {
       update_particle<INTEG, PT, VT, TIER>(x[j], y[j], z[j], u[j], v[j], w[j], ga[j], gb[j],
                                             gc[j], a.dt, p, a.wrap);
     }
-    if constexpr (field_integrator(INTEG)) __builtin_amdgcn_s_setprio(3);
     step_st<STREAM, PT, VEC>(px, first, cnt, e, x);
     step_st<STREAM, PT, VEC>(py, first, cnt, e, y);
     step_st<STREAM, PT, VEC>(pz, first, cnt, e, z);
@@ -791,7 +787,6 @@ __global__ __launch_bounds__(1024) void stream_probe_kernel(ProbeArgs a) {
     V[d] = window(a.vel[d], first, cnt);
   }
   if constexpr (PAT == kProbeRk2) {
-    __builtin_amdgcn_s_setprio(3);
     const double x = win_ld1(P[0], e), y = win_ld1(P[1], e), z = win_ld1(P[2], e);
     win_st1(P[0], e, x + a.c);
     win_st1(P[1], e, y + a.c);

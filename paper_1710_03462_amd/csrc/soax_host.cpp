@@ -232,6 +232,11 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
     // 128 in interleaved runs, RK4 level, Euler 6% slower)
     int vec = set->vec ? set->vec : (field_integrator(integrator) ? 2 : 1);
     if (!set->soa_vec_ok) vec = 1;
+    // four particles per thread would split each 8-byte array's 32-byte run
+    // into two 16-byte accesses, each covering every other half of the wave's
+    // lines: measured 3x slower at 1e8, so 8-byte positions or velocities
+    // take at most two
+    if (vec > 2 && (L.f[fp].es == 8 || L.f[fv].es == 8)) vec = 2;
     const int block = set->block[SOAX_SOA] ? set->block[SOAX_SOA]
                                            : (field_integrator(integrator) ? 64 : 128);
     for (int64_t k = 0; k < nsteps; ++k)

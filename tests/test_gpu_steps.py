@@ -179,6 +179,20 @@ def test_soa_results_do_not_depend_on_launch_shape(integ):
             assert all(np.array_equal(g, b) for g, b in zip(got, base)), (block, vec)
 
 
+def test_float_record_results_do_not_depend_on_launch_shape():
+    # 4-byte positions and velocities: four particles per thread is a single
+    # 16-byte access per array (8-byte arrays are capped at two per thread)
+    fields = si.particle_size_fields(3)
+    n = 10_009
+    arrays = si.random_state(fields, n, seed=5)
+    base = run_gpu(fields, arrays, "soa", "euler", 1e-3, 3, wrap=False)
+    for block in (64, 256):
+        for vec in (1, 2, 4):
+            got = run_gpu(fields, arrays, "soa", "euler", 1e-3, 3, wrap=False, block=block,
+                          per_thread=vec)
+            assert all(np.array_equal(g, b) for g, b in zip(got, base)), (block, vec)
+
+
 @pytest.mark.parametrize("layout", ["aos", "aos_naive"])
 def test_aos_results_do_not_depend_on_block(layout):
     n = 5003
