@@ -188,7 +188,8 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
  * (64..1024, multiple of 64) and particles per thread (1, 2 or 4; SoA only).
  * 0 restores the default: 128 threads (256 for the AoS layouts) and one
  * particle per thread; for the steps in the ABC field (RK2, Heun, RK4) on SoA
- * arrays that are 16-byte aligned, 64 threads and two particles per thread.
+ * arrays that are 16-byte aligned and span at least 128 MB (positions and
+ * velocities), 64 threads and two particles per thread.
  * Heun and RK4 steps, and any step whose positions or velocities are 8-byte
  * elements, take at most two per thread.  Results do not depend on the
  * shape.

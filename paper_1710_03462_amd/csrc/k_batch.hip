@@ -72,48 +72,63 @@ __device__ __forceinline__ void batch_tile(const BatchSet& S, int64_t t, int32_t
 }
 
 // Every tile takes the angle-shift path of its own set's tier (a branch
-// uniform over the workgroup, which works on one tile at a time).
-template <typename VT, int PPT>
+// uniform over the workgroup, which works on one tile at a time).  MAXT, the
+// largest tier of any set in the batch, leaves the paths of larger tiers out
+// of the kernel: the unbounded tier's full-reduction fallback alone raises
+// the kernel's registers (at two particles per thread from about 72 to 100
+// VGPRs, seven resident waves per SIMD to four).
+template <typename VT, int PPT, int MAXT>
 __device__ __forceinline__ void batch_tile_any(const BatchSet& S, int64_t t, int32_t tile) {
-  if (S.tier == kTierSmall)
+  if (MAXT == kTierSmall || S.tier == kTierSmall)
     batch_tile<VT, PPT, kTierSmall>(S, t, tile);
-  else if (S.tier == kTierMid)
+  else if (MAXT == kTierMid || S.tier == kTierMid)
     batch_tile<VT, PPT, kTierMid>(S, t, tile);
   else
     batch_tile<VT, PPT, kTierAny>(S, t, tile);
 }
 
-template <typename VT, int PPT>
+template <typename VT, int PPT, int MAXT>
 __global__ __launch_bounds__(512) void batch_rk2_kernel(BatchLaunch b) {
   for (int64_t t = blockIdx.x; t < b.ntiles; t += gridDim.x)
-    batch_tile_any<VT, PPT>(b.sets[b.tile_set[t]], t, b.tile);
+    batch_tile_any<VT, PPT, MAXT>(b.sets[b.tile_set[t]], t, b.tile);
 }
 
 // The same with one workgroup per tile (the grid covers the tile list).
 // Without the grid-stride loop the kernel needs fewer registers (64 rather
 // than 80 at one particle per thread), so more waves stay resident.
-template <typename VT, int PPT>
+template <typename VT, int PPT, int MAXT>
 __global__ __launch_bounds__(512) void batch_rk2_tile_kernel(BatchLaunch b) {
   const int64_t t = blockIdx.x;
   if (t >= b.ntiles) return;
-  batch_tile_any<VT, PPT>(b.sets[b.tile_set[t]], t, b.tile);
+  batch_tile_any<VT, PPT, MAXT>(b.sets[b.tile_set[t]], t, b.tile);
 }
 
-template <typename VT, int PPT>
+template <typename VT, int PPT, int MAXT>
 void batch_launch_ppt(const BatchLaunch& b, hipStream_t s) {
   if (b.grid >= b.ntiles)
-    hipLaunchKernelGGL((batch_rk2_tile_kernel<VT, PPT>), dim3(b.ntiles), dim3(b.block), 0, s, b);
+    hipLaunchKernelGGL((batch_rk2_tile_kernel<VT, PPT, MAXT>), dim3(b.ntiles), dim3(b.block), 0,
+                       s, b);
   else
-    hipLaunchKernelGGL((batch_rk2_kernel<VT, PPT>), dim3(b.grid), dim3(b.block), 0, s, b);
+    hipLaunchKernelGGL((batch_rk2_kernel<VT, PPT, MAXT>), dim3(b.grid), dim3(b.block), 0, s, b);
+}
+
+template <typename VT, int MAXT>
+void batch_launch_tier(const BatchLaunch& b, hipStream_t s) {
+  switch (b.per_thread) {
+    case 1: batch_launch_ppt<VT, 1, MAXT>(b, s); break;
+    case 2: batch_launch_ppt<VT, 2, MAXT>(b, s); break;
+    default: batch_launch_ppt<VT, 4, MAXT>(b, s); break;
+  }
 }
 
 template <typename VT>
 hipError_t batch_t(const BatchLaunch& b, hipStream_t s) {
-  switch (b.per_thread) {
-    case 1: batch_launch_ppt<VT, 1>(b, s); break;
-    case 2: batch_launch_ppt<VT, 2>(b, s); break;
-    default: batch_launch_ppt<VT, 4>(b, s); break;
-  }
+  if (b.max_tier == kTierSmall)
+    batch_launch_tier<VT, kTierSmall>(b, s);
+  else if (b.max_tier == kTierMid)
+    batch_launch_tier<VT, kTierMid>(b, s);
+  else
+    batch_launch_tier<VT, kTierAny>(b, s);
   return hipGetLastError();
 }
 

@@ -200,8 +200,7 @@ hipError_t soa_step_vec(int vec, int block, const SoaStepArgs& a, hipStream_t s)
   const int64_t threads = (a.n + vec - 1) / vec;
   const int64_t grid = (threads + block - 1) / block;
   if (grid == 0) return hipSuccess;
-  int64_t bytes = 3 * (sizeof(PT) + sizeof(VT));
-  if (uses_acc(INTEG)) bytes += 3 * sizeof(VT);
+  const int64_t bytes = soa_step_bytes(INTEG, sizeof(PT), sizeof(VT));
   const bool stream = a.n * bytes >= kStreamBytes;
   if constexpr (field_integrator(INTEG)) {
     const int tier = shift_tier(a.dt, a.abc.A, a.abc.B, a.abc.C);

@@ -72,6 +72,12 @@ inline __host__ __device__ int shift_tier(double dt, double A, double B, double 
 // steps and use ordinary accesses.
 constexpr int64_t kStreamBytes = int64_t(128) << 20;
 
+// Bytes of one particle the SoA step reads or writes: positions and
+// velocities, plus the acceleration for the integrators that use it.
+inline int64_t soa_step_bytes(int integ, int pos_size, int vel_size) {
+  return 3 * (pos_size + vel_size) + (uses_acc(integ) ? 3 * vel_size : 0);
+}
+
 // ------------------------------------------------------------------ steps
 
 struct SoaStepArgs {
@@ -344,6 +350,7 @@ struct BatchLaunch {
   int32_t per_thread;
   int32_t grid;
   int32_t vel_t;
+  int32_t max_tier;  // the largest shift tier of any set (the kernel handles tiers up to it)
 };
 hipError_t launch_batch_rk2(const BatchLaunch& b, hipStream_t s);
 

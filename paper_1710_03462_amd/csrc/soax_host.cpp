@@ -224,21 +224,25 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
     a.dt = dt;
     a.abc = abc;
     a.wrap = wrap;
-    // one particle per thread in workgroups of 128, except two consecutive
-    // particles (16-byte position accesses) in workgroups of 64 for the field
-    // integrators: the fastest shapes measured on the MI355X at 1e8
-    // particles (two per thread: RK2 and Heun 3% faster than one, RK4 2%,
-    // Euler 10% slower; then 64 threads: RK2 and Heun about 1% faster than
-    // 128 in interleaved runs, RK4 level, Euler 6% slower)
-    int vec = set->vec ? set->vec : (field_integrator(integrator) ? 2 : 1);
+    // one particle per thread in workgroups of 128, except, for the field
+    // integrators on sets that stream through HBM, two consecutive particles
+    // (16-byte position accesses) in workgroups of 64: the fastest shapes
+    // measured on the MI355X at 1e8 particles (two per thread: RK2 and Heun
+    // 3% faster than one, RK4 2%, Euler 10% slower; then 64 threads: RK2 and
+    // Heun about 1% faster than 128 in interleaved runs, RK4 level, Euler 6%
+    // slower).  Cache-resident sets are bound by latency, and there the wider
+    // shape was slower (one launch per set over 256 sets of 1e3..1e6
+    // particles: 174 ms against 150 ms for 100 steps).
+    const bool wide = field_integrator(integrator) &&
+                      set->n * soa_step_bytes(integrator, L.f[fp].es, L.f[fv].es) >= kStreamBytes;
+    int vec = set->vec ? set->vec : (wide ? 2 : 1);
     if (!set->soa_vec_ok) vec = 1;
     // four particles per thread would split each 8-byte array's 32-byte run
     // into two 16-byte accesses, each covering every other half of the wave's
     // lines: measured 3x slower at 1e8, so 8-byte positions or velocities
     // take at most two
     if (vec > 2 && (L.f[fp].es == 8 || L.f[fv].es == 8)) vec = 2;
-    const int block = set->block[SOAX_SOA] ? set->block[SOAX_SOA]
-                                           : (field_integrator(integrator) ? 64 : 128);
+    const int block = set->block[SOAX_SOA] ? set->block[SOAX_SOA] : (wide ? 64 : 128);
     for (int64_t k = 0; k < nsteps; ++k)
       HIP_TRY(launch_soa_step(integrator, L.f[fp].dtype, L.f[fv].dtype, vec, block, a, s),
               "SoA step launch");

@@ -121,6 +121,27 @@ def test_graph_replays_match_eager():
         assert same(download(gsets), download(esets)), rep
 
 
+def test_graphs_follow_the_largest_tier_of_the_step():
+    # the batch kernel is instantiated for the largest shift tier among the
+    # sets: a graph captured while every set is in the small tier must not be
+    # replayed once a set needs the mid or the unbounded tier
+    k = len(SIZES)
+    _, abc = plan(k)
+    small = np.full(k, 1e-3)
+    mixed = small.copy()
+    mixed[2] = 0.02  # dt (|A|+|B|+|C|) in (1/64, 1/8]: mid tier
+    mixed[5] = 0.2   # beyond 1/8: unbounded tier
+    gsets, _ = make_sets(SIZES, seed=9)
+    gb = soax.Batch(gsets)
+    for dts in (small, mixed, small, mixed):
+        gb.step(dts, abc, 3, mode=soax.GRAPH)
+    ssets, _ = make_sets(SIZES, seed=9)
+    for dts in (small, mixed, small, mixed):
+        for i, ps in enumerate(ssets):
+            ps.step("soa", "rk2_abc", dts[i], 3, abc=abc[i], wrap=True)
+    assert same(download(gsets), download(ssets))
+
+
 def test_tuner_keeps_state_and_writes_cache(tmp_path):
     dts, abc = plan(len(SIZES))
     sets, _ = make_sets(SIZES, seed=5)
