@@ -124,6 +124,39 @@ def test_field_integrators_streaming_whole_arrays_4e6(ref, layout, integ):
 _FIELD_SOA = {}
 
 
+N_PAIRS = 3_840_000  # a multiple of 512: whole pairs of runs for runs of 128 and 256 particles
+
+
+@pytest.mark.parametrize("block,per_thread", [(64, 2), (128, 2), (64, 1)])
+@pytest.mark.parametrize("extra", [0, 5, 128, 200, 256 + 77])
+def test_rk4_streaming_pairs_of_runs_match_aos(block, per_thread, extra):
+    # the streaming RK4 step takes two runs of block * per_thread particles per
+    # workgroup and steps an incomplete last pair one particle per thread:
+    # every split of the last pair (none, a partial first run, one whole run,
+    # a whole run and a partial one) must give the LDS-staged AoS kernel's
+    # results bit for bit
+    n = N_PAIRS + extra
+    fields = si.BASE_FIELDS
+    assert n * 36 >= STREAM_BYTES
+    arrays = si.random_state(fields, n, seed=53)
+    abc = [1.0, 0.8, 0.6]
+    soa = soax.ParticleSet(fields, n, aos=False)
+    soa.upload_soa(arrays)
+    soa.step_config("soa", block, per_thread)
+    soa.step("soa", "rk4_abc", 2e-3, 2, abc=abc, wrap=True)
+    aos = soax.ParticleSet(fields, n, soa=False)
+    aos.upload_aos(to_aos(fields, arrays))
+    aos.step("aos", "rk4_abc", 2e-3, 2, abc=abc, wrap=True)
+    torch.cuda.synchronize()
+    got = soa.download_soa()
+    want = from_aos(fields, aos.download_aos(), n)
+    soa.close()
+    aos.close()
+    for a, (g, w) in enumerate(zip(got, want)):
+        assert np.array_equal(g, w), a
+    assert not np.array_equal(got[1], arrays[1])  # the step moved the particles
+
+
 
 def test_euler_headline_1e8_every_layout(ref):
     """The benchmark's Euler rows: 20 steps in SoA, 20 in the LDS-staged AoS
