@@ -4,11 +4,11 @@
 // The step (Section 2, eq. (1) and its RK2 / acceleration variants) is a
 // streaming read-modify-write with no reuse inside a step, so the kernels are
 // shaped for HBM, not for the matrix cores:
-//  * SoA: each thread owns `VEC` consecutive particles (1 by default, the
-//    fastest shape measured here; 2 or 4 give 16-byte accesses), so a wave
-//    reads and writes each array it touches as one contiguous run; arrays the
-//    step does not use (id, mass, ...) are never read, the SoA advantage of
-//    Section 2.
+//  * SoA: each thread owns `VEC` consecutive particles (one by default; two,
+//    with 16-byte position accesses, for the field integrators on sets that
+//    stream from HBM, where that shape measured fastest), so a wave reads and
+//    writes each array it touches as one contiguous run; arrays the step does
+//    not use (id, mass, ...) are never read, the SoA advantage of Section 2.
 //  * AoS: a workgroup stages a tile of whole records through LDS with
 //    coalesced 16-byte accesses, updates the records in LDS and writes the
 //    tile back, so the only waste is the bytes of unused fields, not the
