@@ -15,7 +15,9 @@ versus one launch per set (tuned shape), removal of a seeded 1% of the
 headline set by overwriting with the last particle, and fused array
 expressions on the headline set (fused versus one launch per operation).
 "copy" is the 16-byte copy kernel's bandwidth on 4 GiB, the achievable HBM
-ceiling.
+ceiling.  "fused_extra" is a labelled extra outside the benchmarked method:
+every step of a job in one launch with the particles held in registers
+(bit-identical results, one pass over memory per job instead of per step).
 
 Prints ONE JSON line on stdout (progress goes to stderr).
 """
@@ -115,6 +117,31 @@ def bench_integrators(torch, soax, ps, n, nsteps=10):
             per = t.ms / nsteps
             out[f"{integ}_{lay}"] = {"updates_per_s": rate(n * nsteps, t.ms), "ms_per_launch": per,
                                      "alg_GBps": gbs(60 * n, per)}
+    return out
+
+
+def bench_fused(torch, soax, si, ps, n, nsteps, stepwise_ms):
+    """A labelled extra, not the benchmarked method (which passes over every
+    array at each step): nsteps steps in one launch with every particle held
+    in registers (soax_step_fused, bit-identical to the separate steps), on
+    the headline set (RK2, and Euler) and on the 1e5-particle Euler workload.
+    Bound by fp64 arithmetic instead of HBM; the arrays move once per job."""
+    out = {}
+    for integ, abc in (("rk2_abc", [1, 1, 1]), ("euler", None)):
+        ps.step_fused(integ, 1e-3, 2, abc=abc, wrap=True)
+        with Timer(torch) as t:
+            ps.step_fused(integ, 1e-3, nsteps, abc=abc, wrap=True)
+        out[f"{integ}_1e8"] = {"nsteps": nsteps, "ms": t.ms, "updates_per_s": rate(n * nsteps, t.ms)}
+    out["rk2_abc_1e8"]["over_stepwise"] = stepwise_ms / out["rk2_abc_1e8"]["ms"]
+    small_n, small_steps = 100_000, 100
+    small = soax.ParticleSet(si.BASE_FIELDS, small_n, aos=False)
+    small.fill(seed=0)
+    small.step_fused("euler", 1e-3, small_steps, wrap=True)
+    with Timer(torch) as t:
+        small.step_fused("euler", 1e-3, small_steps, wrap=True)
+    out["euler_1e5"] = {"nsteps": small_steps, "ms": t.ms,
+                        "updates_per_s": rate(small_n * small_steps, t.ms)}
+    small.close()
     return out
 
 
@@ -767,7 +794,7 @@ def main():
     ap.add_argument("--n", type=float, default=1e8, help="particles of the headline workload")
     ap.add_argument("--rows", default="all",
                     help="comma list of extra rows: aos,euler,small,copy,probes,wide,adjoint,"
-                         "batch,remove,expr,expr_euler,integrators,aosoa | all | none")
+                         "batch,remove,expr,expr_euler,integrators,aosoa,fused | all | none")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--sweep", action="store_true",
                     help="run only the N x SIZE sweep of the paper's GPU experiment and print "
@@ -810,7 +837,7 @@ def main():
                           "device": torch.cuda.get_device_name(0)}), flush=True)
         return 0
     rows = {"aos", "euler", "small", "copy", "probes", "wide", "adjoint", "batch", "remove",
-            "expr", "expr_euler", "integrators", "aosoa"} \
+            "expr", "expr_euler", "integrators", "aosoa", "fused"} \
         if args.rows == "all" else \
         set() if args.rows == "none" else set(args.rows.split(","))
     n = int(args.n)
@@ -855,6 +882,9 @@ def main():
     if "integrators" in rows:
         log("[bench] Heun and RK4 steps at the headline size")
         out_rows["integrators"] = bench_integrators(torch, soax, ps, n)
+    if "fused" in rows:
+        log("[bench] extra: all steps of a job in one launch (particles held in registers)")
+        out_rows["fused_extra"] = bench_fused(torch, soax, si, ps, n, nsteps, ms_per_step)
     ps.close()
     del ps
     torch.cuda.empty_cache()

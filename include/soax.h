@@ -184,6 +184,23 @@ soax_status soax_step(soax_set* set, int32_t layout, int32_t integrator, double 
                       const soax_params* params, void* stream);
 
 /*
+ * nsteps time steps of `integrator` on the SoA arrays in one launch, each
+ * particle held in registers from the first step to the last, so the arrays
+ * are read and written once per call instead of once per step.  This is not
+ * the loop the paper benchmarks (Section 2 passes over every array at each
+ * step, which is what soax_step does); it is offered beside it for callers
+ * that need nothing between the steps.  Every step is the same arithmetic as
+ * soax_step's, so the results equal soax_step(set, SOAX_SOA, integrator, dt,
+ * nsteps, params, stream) bit for bit; for the field integrators the
+ * velocity (which no step reads) is evaluated once, at the final position.
+ * One thread per particle, 256-thread workgroups.  Arguments and errors as
+ * soax_step; a single launch runs every step, so its duration grows with
+ * nsteps.
+ */
+soax_status soax_step_fused(soax_set* set, int32_t integrator, double dt, int64_t nsteps,
+                            const soax_params* params, void* stream);
+
+/*
  * Override the launch shape of soax_step for one layout: block threads
  * (64..1024, multiple of 64) and particles per thread (1, 2 or 4; SoA only).
  * 0 restores the default: 128 threads (256 for the AoS layouts) and one

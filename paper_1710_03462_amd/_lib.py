@@ -74,6 +74,7 @@ def lib():
         "soax_buffer": [vp, i32, vp],
         "soax_fill": [vp, u64, i32, pp, vp],
         "soax_step": [vp, i32, i32, dbl, i64, pp, vp],
+        "soax_step_fused": [vp, i32, dbl, i64, pp, vp],
         "soax_step_config": [vp, i32, i32, i32],
         "soax_aos_to_soa": [vp, vp],
         "soax_soa_to_aos": [vp, vp],

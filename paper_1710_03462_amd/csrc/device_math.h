@@ -338,6 +338,28 @@ __device__ __forceinline__ void rk4_parts(const Abc& p, double dt, double x, dou
   d2 = s * (k12 + 2.0 * k22 + 2.0 * k32 + k42);
 }
 
+// The positions (y0, y1, y2) one step of a field integrator after
+// (s0, s1, s2), not wrapped; t: the start point's sines and cosines, d: the
+// displacement, from which the field at the new position follows by angle
+// addition.
+template <int INTEG, int TIER>
+__device__ __forceinline__ void field_step(const Abc& p, double dt, double s0, double s1,
+                                           double s2, double& y0, double& y1, double& y2,
+                                           Trig3& t, double& d0, double& d1, double& d2) {
+  if constexpr (INTEG == kRk2Abc) {
+    y0 = s0;
+    y1 = s1;
+    y2 = s2;
+    rk2_midpoint_parts<TIER>(p, dt, y0, y1, y2, t, d0, d1, d2);
+  } else {
+    if constexpr (INTEG == kHeunAbc) heun_parts<TIER>(p, dt, s0, s1, s2, t, d0, d1, d2);
+    else rk4_parts<TIER>(p, dt, s0, s1, s2, t, d0, d1, d2);
+    y0 = s0 + d0;
+    y1 = s1 + d1;
+    y2 = s2 + d2;
+  }
+}
+
 // Advance one particle.  Positions and velocities are widened to double,
 // combined in double and rounded back on store.  TIER: shift_tier of the
 // step (field integrators only; the results do not depend on it).
@@ -370,18 +392,10 @@ __device__ __forceinline__ void update_particle(PT& x0, PT& x1, PT& x2, VT& v0, 
     }
   } else {
     const double s0 = widen(x0), s1 = widen(x1), s2 = widen(x2);
-    double y0 = s0, y1 = s1, y2 = s2;
+    double y0, y1, y2;
     Trig3 t;
     double d0, d1, d2;
-    if constexpr (INTEG == kRk2Abc) {
-      rk2_midpoint_parts<TIER>(p, dt, y0, y1, y2, t, d0, d1, d2);
-    } else {
-      if constexpr (INTEG == kHeunAbc) heun_parts<TIER>(p, dt, s0, s1, s2, t, d0, d1, d2);
-      else rk4_parts<TIER>(p, dt, s0, s1, s2, t, d0, d1, d2);
-      y0 = s0 + d0;
-      y1 = s1 + d1;
-      y2 = s2 + d2;
-    }
+    field_step<INTEG, TIER>(p, dt, s0, s1, s2, y0, y1, y2, t, d0, d1, d2);
     if (wrap) {
       y0 = wrap_box(y0);
       y1 = wrap_box(y1);

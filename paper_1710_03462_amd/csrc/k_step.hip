@@ -295,6 +295,88 @@ hipError_t soa_step_vec(int vec, int block, const SoaStepArgs& a, hipStream_t s)
   return soa_step_stream<INTEG, PT, VT, kTierAny>(stream, vec, grid, block, a, s);
 }
 
+// ---------------------------------------------------------- fused steps
+
+// nsteps steps of one particle per thread with the particle held in registers
+// in between: the arrays are read and written once per launch instead of once
+// per step.  Each step is the arithmetic of update_particle, so the results
+// equal nsteps launches of the one-step kernels bit for bit; for the field
+// integrators the velocity, which no step reads, is evaluated once, at the
+// final position, from the last step's sines, cosines and displacement.
+template <int INTEG, typename PT, typename VT, int TIER>
+__global__ __launch_bounds__(256) void soa_fused_kernel(SoaStepArgs a, int64_t nsteps) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const Abc p = to_abc(a.abc);
+  PT* px = static_cast<PT*>(a.pos[0]);
+  PT* py = static_cast<PT*>(a.pos[1]);
+  PT* pz = static_cast<PT*>(a.pos[2]);
+  VT* vx = static_cast<VT*>(a.vel[0]);
+  VT* vy = static_cast<VT*>(a.vel[1]);
+  VT* vz = static_cast<VT*>(a.vel[2]);
+  PT x = px[i], y = py[i], z = pz[i];
+  if constexpr (field_integrator(INTEG)) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    Trig3 t{};
+    for (int64_t k = 0; k < nsteps; ++k) {
+      s0 = x;
+      s1 = y;
+      s2 = z;
+      double y0, y1, y2;
+      field_step<INTEG, TIER>(p, a.dt, s0, s1, s2, y0, y1, y2, t, d0, d1, d2);
+      if (a.wrap) {
+        y0 = wrap_box(y0);
+        y1 = wrap_box(y1);
+        y2 = wrap_box(y2);
+      }
+      x = y0;
+      y = y1;
+      z = y2;
+    }
+    double u0, u1, u2;
+    field_of(p, trig3_shift<TIER>(t, s0, s1, s2, d0, d1, d2), u0, u1, u2);
+    vx[i] = static_cast<VT>(u0);
+    vy[i] = static_cast<VT>(u1);
+    vz[i] = static_cast<VT>(u2);
+  } else {
+    VT u = vx[i], v = vy[i], w = vz[i];
+    VT g0 = VT(0), g1 = VT(0), g2 = VT(0);
+    if constexpr (uses_acc(INTEG)) {
+      g0 = static_cast<const VT*>(a.acc[0])[i];
+      g1 = static_cast<const VT*>(a.acc[1])[i];
+      g2 = static_cast<const VT*>(a.acc[2])[i];
+    }
+    for (int64_t k = 0; k < nsteps; ++k)
+      update_particle<INTEG, PT, VT, kTierAny>(x, y, z, u, v, w, g0, g1, g2, a.dt, p, a.wrap);
+    if constexpr (INTEG != kEuler) {
+      vx[i] = u;
+      vy[i] = v;
+      vz[i] = w;
+    }
+  }
+  px[i] = x;
+  py[i] = y;
+  pz[i] = z;
+}
+
+template <int INTEG, typename PT, typename VT>
+hipError_t soa_fused_launch(int block, const SoaStepArgs& a, int64_t nsteps, hipStream_t s) {
+  const int64_t grid = (a.n + block - 1) / block;
+  if (grid == 0 || nsteps <= 0) return hipSuccess;
+  int tier = kTierAny;
+  if constexpr (field_integrator(INTEG)) tier = shift_tier(a.dt, a.abc.A, a.abc.B, a.abc.C);
+  if (tier == kTierSmall)
+    hipLaunchKernelGGL((soa_fused_kernel<INTEG, PT, VT, kTierSmall>), dim3(grid), dim3(block), 0,
+                       s, a, nsteps);
+  else if (tier == kTierMid)
+    hipLaunchKernelGGL((soa_fused_kernel<INTEG, PT, VT, kTierMid>), dim3(grid), dim3(block), 0,
+                       s, a, nsteps);
+  else
+    hipLaunchKernelGGL((soa_fused_kernel<INTEG, PT, VT, kTierAny>), dim3(grid), dim3(block), 0,
+                       s, a, nsteps);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------- AoS element access
 
 template <typename T, bool ALIGNED>
@@ -898,6 +980,43 @@ __global__ __launch_bounds__(1024) void stream_probe_kernel(ProbeArgs a) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+
+hipError_t launch_soa_fused(int integ, int pos_t, int vel_t, int block, const SoaStepArgs& a,
+                            int64_t nsteps, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const bool pd = pos_t == kF64, vd = vel_t == kF64;
+  switch (integ) {
+    case kEuler:
+      if (pd && !vd) return soa_fused_launch<kEuler, double, float>(block, a, nsteps, s);
+      if (pd && vd) return soa_fused_launch<kEuler, double, double>(block, a, nsteps, s);
+      if (!pd && !vd) return soa_fused_launch<kEuler, float, float>(block, a, nsteps, s);
+      return soa_fused_launch<kEuler, float, double>(block, a, nsteps, s);
+    case kEulerAcc:
+      if (pd && !vd) return soa_fused_launch<kEulerAcc, double, float>(block, a, nsteps, s);
+      if (pd && vd) return soa_fused_launch<kEulerAcc, double, double>(block, a, nsteps, s);
+      if (!pd && !vd) return soa_fused_launch<kEulerAcc, float, float>(block, a, nsteps, s);
+      return soa_fused_launch<kEulerAcc, float, double>(block, a, nsteps, s);
+    case kSymEuler:
+      if (pd && !vd) return soa_fused_launch<kSymEuler, double, float>(block, a, nsteps, s);
+      if (pd && vd) return soa_fused_launch<kSymEuler, double, double>(block, a, nsteps, s);
+      if (!pd && !vd) return soa_fused_launch<kSymEuler, float, float>(block, a, nsteps, s);
+      return soa_fused_launch<kSymEuler, float, double>(block, a, nsteps, s);
+    case kRk2Abc:
+      if (!pd) return hipErrorInvalidValue;
+      if (vd) return soa_fused_launch<kRk2Abc, double, double>(block, a, nsteps, s);
+      return soa_fused_launch<kRk2Abc, double, float>(block, a, nsteps, s);
+    case kHeunAbc:
+      if (!pd) return hipErrorInvalidValue;
+      if (vd) return soa_fused_launch<kHeunAbc, double, double>(block, a, nsteps, s);
+      return soa_fused_launch<kHeunAbc, double, float>(block, a, nsteps, s);
+    case kRk4Abc:
+      if (!pd) return hipErrorInvalidValue;
+      if (vd) return soa_fused_launch<kRk4Abc, double, double>(block, a, nsteps, s);
+      return soa_fused_launch<kRk4Abc, double, float>(block, a, nsteps, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_soa_step(int integ, int pos_t, int vel_t, int vec, int block,
                            const SoaStepArgs& a, hipStream_t s) {

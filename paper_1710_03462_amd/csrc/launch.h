@@ -94,6 +94,11 @@ struct SoaStepArgs {
 hipError_t launch_soa_step(int integ, int pos_t, int vel_t, int vec, int block,
                            const SoaStepArgs& a, hipStream_t s);
 
+// nsteps (>= 1) steps of integ in one launch, each particle held in registers
+// from the first step to the last (one thread per particle).
+hipError_t launch_soa_fused(int integ, int pos_t, int vel_t, int block, const SoaStepArgs& a,
+                            int64_t nsteps, hipStream_t s);
+
 struct AosStepArgs {
   char* aos;
   int64_t n;

@@ -310,6 +310,35 @@ static soax_status xpose(soax_set* set, bool to_soa, void* stream) {
   return SOAX_OK;
 }
 
+soax_status soax_step_fused(soax_set* set, int32_t integrator, double dt, int64_t nsteps,
+                            const soax_params* params, void* stream) {
+  // every argument check of soax_step on the SoA arrays, with nothing launched
+  soax_status st = soax_step(set, SOAX_SOA, integrator, dt, 0, params, nullptr);
+  if (st) return st;
+  if (nsteps < 0) return fail(SOAX_E_ARG, "nsteps is negative");
+  const Layout& L = set->L;
+  int fp, fv, fa = -1;
+  (void)vec_field(L, "pos", &fp);
+  (void)vec_field(L, "vel", &fv);
+  if (uses_acc(integrator)) (void)vec_field(L, "acc", &fa);
+  SoaStepArgs a{};
+  for (int d = 0; d < 3; ++d) {
+    a.pos[d] = set->soa[L.f[fp].first_array + d];
+    a.vel[d] = set->soa[L.f[fv].first_array + d];
+    a.acc[d] = fa >= 0 ? set->soa[L.f[fa].first_array + d] : nullptr;
+  }
+  a.n = set->n;
+  a.dt = dt;
+  if (params) a.abc = AbcParams{params->A, params->B, params->C};
+  a.wrap = params ? params->wrap : 0;
+  // one particle per thread: the loop over steps is bound by arithmetic, and
+  // the arrays are touched once per call
+  HIP_TRY(launch_soa_fused(integrator, L.f[fp].dtype, L.f[fv].dtype, 256, a, nsteps,
+                           as_stream(stream)),
+          "fused SoA step launch");
+  return SOAX_OK;
+}
+
 soax_status soax_aos_to_soa(soax_set* set, void* stream) { return xpose(set, true, stream); }
 soax_status soax_soa_to_aos(soax_set* set, void* stream) { return xpose(set, false, stream); }
 

@@ -252,6 +252,14 @@ class ParticleSet:
         check(lib().soax_step(self.handle, lay, integ, float(dt), int(nsteps), ctypes.byref(p),
                               current_stream()), "soax_step")
 
+    def step_fused(self, integrator, dt, nsteps, abc=None, wrap=True):
+        """nsteps SoA steps in one launch with every particle held in registers
+        in between; the same results as step("soa", ...), bit for bit."""
+        integ = _lib.INTEGRATORS[integrator] if isinstance(integrator, str) else integrator
+        p = params(abc, wrap)
+        check(lib().soax_step_fused(self.handle, integ, float(dt), int(nsteps), ctypes.byref(p),
+                                    current_stream()), "soax_step_fused")
+
     def step_graph(self, layout, integrator, dt, nsteps, abc=None, wrap=True):
         """The nsteps launches of step() captured once; call .launch() to replay."""
         return StepGraph(self, layout, integrator, dt, nsteps, abc, wrap)

@@ -42,7 +42,7 @@ def test_header_declarations_match_binding_signatures():
              "soax_rk2_forward_ckpt_strided", "soax_adjoint_strided", "soax_sqdist_loss_strided",
              "soax_aosoa_layout", "soax_bind_aosoa", "soax_soa_to_aosoa", "soax_aosoa_to_soa",
              "soax_step_graph_create", "soax_step_graph_launch", "soax_step_graph_destroy",
-             "soax_adjoint_noalloc", "soax_probe"}
+             "soax_adjoint_noalloc", "soax_probe", "soax_step_fused"}
     assert declared == bound
 
 
