@@ -403,7 +403,7 @@ soax_status soax_expr_source(const soax_expr_op* prog, int32_t nops, int32_t dst
  * position, rows 3..8 sin x, cos x, sin y, cos y, sin z, cos z as the
  * forward evaluated them.  When |dt| (|A| + |B| + |C|) <= 1/64 every step's
  * sines and cosines come from the previous step's by angle addition, with a
- * full evaluation every 16 steps; the results depend on the step index only,
+ * full evaluation every 20 steps; the results depend on the step index only,
  * never on k.  Errors: ARG (NULL array or tape, n < 0, nsteps < 0, k < 1,
  * non-finite dt or amplitude), RANGE (n > 2^31-1), HIP.
  */

@@ -36,29 +36,49 @@ constexpr int kTapeRows = 9;
 // full reduction at every step index that is a multiple of kAnchor, so each
 // value depends on the step index alone (not on the checkpoint interval) and
 // carries at most kAnchor - 1 angle additions (about one ulp of 1 each).
-// Larger steps reduce every state in full.
-constexpr int64_t kAnchor = 16;
+// Larger steps reduce every state in full.  kAnchor equals the register
+// block of the usual checkpoint interval (20), so that a block that starts
+// at a multiple of it has no renewal inside its recomputation and exactly
+// one, at its first reversed state, in the reverse sweep: such blocks run as
+// straight-line code (adjoint_blocks_kernel).
+constexpr int64_t kAnchor = 20;
 
 // The angle-shift tier of these kernels: SMALL (small_steps holds) or any shift.
 template <bool SMALL>
 constexpr int kTierOf = SMALL ? kTierSmall : kTierAny;
 
 // One explicit-midpoint step from (x, y, z) with sines and cosines t, no
-// wrap; on return (x, y, z) is the state of step s + 1 and t its sines and
-// cosines as above.  (dt/2) k1 and dt k2 are the fields of the amplitudes
-// scaled by dt/2 and dt, which a loop computes once.
+// wrap; on return (x, y, z) is the next state and t its sines and cosines as
+// above (renew: the next state's index is a multiple of kAnchor).  (dt/2) k1
+// and dt k2 are the fields of the amplitudes scaled by dt/2 and dt, which a
+// loop computes once.
 template <bool SMALL>
-__device__ __forceinline__ void rk2_advance(const Abc& p, double dt, int64_t s, double& x,
+__device__ __forceinline__ void rk2_advance(const Abc& p, double dt, bool renew, double& x,
                                             double& y, double& z, Trig3& t) {
   double m0, m1, m2;
   field_of(scaled(p, 0.5 * dt), t, m0, m1, m2);
   const Trig3 tm = trig3_shift<kTierOf<SMALL>>(t, x, y, z, m0, m1, m2);
   field_of(scaled(p, dt), tm, m0, m1, m2);
   const double x1 = x + m0, y1 = y + m1, z1 = z + m2;
-  if (!SMALL || (s + 1) % kAnchor == 0)
+  if (!SMALL || renew)
     t = trig3(x1, y1, z1);
   else
     t = trig3_shift<kTierOf<SMALL>>(t, x, y, z, x1 - x, y1 - y, z1 - z);
+  x = x1;
+  y = y1;
+  z = z1;
+}
+
+// rk2_advance<true> for a step whose next state is not a renewal point: the
+// same arithmetic without the branch.
+__device__ __forceinline__ void rk2_advance_carry(const Abc& p, double dt, double& x, double& y,
+                                                  double& z, Trig3& t) {
+  double m0, m1, m2;
+  field_of(scaled(p, 0.5 * dt), t, m0, m1, m2);
+  const Trig3 tm = trig3_shift<kTierSmall>(t, x, y, z, m0, m1, m2);
+  field_of(scaled(p, dt), tm, m0, m1, m2);
+  const double x1 = x + m0, y1 = y + m1, z1 = z + m2;
+  t = trig3_shift<kTierSmall>(t, x, y, z, x1 - x, y1 - y, z1 - z);
   x = x1;
   y = y1;
   z = z1;
@@ -75,6 +95,7 @@ __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
   double* tp = a.tape + i;
   const int64_t n = a.n;
   int64_t until_ckpt = 0;
+  int r = 1;  // (s + 1) mod kAnchor, kept by counting
   for (int64_t s = 0; s < a.nsteps; ++s) {
     if (until_ckpt == 0) {  // the tape is written once and read back much later
       st1<true>(tp, x);
@@ -90,7 +111,45 @@ __global__ __launch_bounds__(256) void rk2_ckpt_kernel(CkptArgs a) {
       until_ckpt = a.k;
     }
     --until_ckpt;
-    rk2_advance<SMALL>(p, a.dt, s, x, y, z, t);
+    rk2_advance<SMALL>(p, a.dt, r == 0, x, y, z, t);
+    r = r + 1 == kAnchor ? 0 : r + 1;
+  }
+  st1<true>(a.xT[0] + e, x);
+  st1<true>(a.xT[1] + e, y);
+  st1<true>(a.xT[2] + e, z);
+}
+
+// rk2_ckpt_kernel<true> when k and nsteps are multiples of kAnchor: the
+// steps run in blocks of kAnchor that start at renewal points, each kAnchor
+// - 1 carried steps and one renewed step as straight-line code (the same
+// values; without a branch per step the compiler overlaps consecutive
+// steps).  Every checkpoint falls on a block's start.
+__global__ __launch_bounds__(256) void rk2_ckpt_blocks_kernel(CkptArgs a) {
+  constexpr int KB = static_cast<int>(kAnchor);
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const Abc p = to_abc(a.abc);
+  const int64_t e = i * a.stride;
+  double x = a.x0[0][e], y = a.x0[1][e], z = a.x0[2][e];
+  Trig3 t = trig3(x, y, z);
+  double* tp = a.tape + i;
+  const int64_t n = a.n;
+  for (int64_t s0 = 0; s0 < a.nsteps; s0 += KB) {
+    if (s0 % a.k == 0) {
+      st1<true>(tp, x);
+      st1<true>(tp + n, y);
+      st1<true>(tp + 2 * n, z);
+      st1<true>(tp + 3 * n, t.sx);
+      st1<true>(tp + 4 * n, t.cx);
+      st1<true>(tp + 5 * n, t.sy);
+      st1<true>(tp + 6 * n, t.cy);
+      st1<true>(tp + 7 * n, t.sz);
+      st1<true>(tp + 8 * n, t.cz);
+      tp += kTapeRows * n;
+    }
+#pragma unroll
+    for (int j = 0; j < KB - 1; ++j) rk2_advance_carry(p, a.dt, x, y, z, t);
+    rk2_advance<true>(p, a.dt, true, x, y, z, t);
   }
   st1<true>(a.xT[0] + e, x);
   st1<true>(a.xT[1] + e, y);
@@ -183,8 +242,12 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
       for (int64_t q = nsub - 1; q >= 0; --q) {
         double x = cp[0], y = cp[n], z = cp[2 * n];
         Trig3 t{cp[3 * n], cp[4 * n], cp[5 * n], cp[6 * n], cp[7 * n], cp[8 * n]};
-        int64_t s = c * a.k;  // global index of the state (x, y, z)
-        for (; s < c * a.k + q * KM; ++s) rk2_advance<SMALL>(p, dt, s, x, y, z, t);
+        // r: (index of the state after the next step) mod kAnchor, by counting
+        int r = static_cast<int>((c * a.k + 1) % kAnchor);
+        for (int64_t s = c * a.k; s < c * a.k + q * KM; ++s) {
+          rk2_advance<SMALL>(p, dt, r == 0, x, y, z, t);
+          r = r + 1 == kAnchor ? 0 : r + 1;
+        }
         const int m = static_cast<int>(min(static_cast<int64_t>(KM), len - q * KM));
         double sx[KM], sy[KM], sz[KM];
 #pragma unroll
@@ -193,16 +256,21 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
             sx[j] = x;
             sy[j] = y;
             sz[j] = z;
-            if (j + 1 < m) rk2_advance<SMALL>(p, dt, s + j, x, y, z, t);
+            if (j + 1 < m) rk2_advance<SMALL>(p, dt, r == 0, x, y, z, t);
+            r = r + 1 == kAnchor ? 0 : r + 1;
           }
         }
         const int64_t t0 = c * a.k + q * KM;  // global index of state 0
+        const int r0 = static_cast<int>(t0 % kAnchor);
 #pragma unroll
         for (int j = KM - 1; j >= 0; --j) {
           if (j < m) {
             const int64_t ts = t0 + j;
+            int rj = r0 + j;  // ts mod kAnchor (r0 + j < 3 kAnchor)
+            if (rj >= kAnchor) rj -= kAnchor;
+            if (rj >= kAnchor) rj -= kAnchor;
             Trig3 tj;
-            if (!SMALL || ts == a.nsteps - 1 || ts % kAnchor == kAnchor - 1)
+            if (!SMALL || ts == a.nsteps - 1 || rj == kAnchor - 1)
               tj = trig3(sx[j], sy[j], sz[j]);
             else
               tj = trig3_shift<kTierOf<SMALL>>(tn, xn, yn, zn, sx[j] - xn, sy[j] - yn, sz[j] - zn);
@@ -212,6 +280,64 @@ __global__ __launch_bounds__(kRedBlock) void adjoint_kernel(AdjointArgs a) {
             yn = sy[j];
             zn = sz[j];
           }
+        }
+      }
+    }
+    a.gx[0][e] = l0;
+    a.gx[1][e] = l1;
+    a.gx[2][e] = l2;
+  }
+  block_sum3(g0, g1, g2, a.partial + 3 * static_cast<int64_t>(blockIdx.x));
+}
+
+// The adjoint when every step is small and both k and nsteps are multiples
+// of kAnchor: every segment's length is then a multiple of kAnchor too, and
+// every block of kAnchor states starts at a renewal point (its first
+// state's index is a multiple of kAnchor).  Its states t0 + 1 ..
+// t0 + kAnchor - 1 are not renewal points, so the recomputation only carries;
+// the reverse sweep renews at the block's last state (index kAnchor - 1
+// modulo kAnchor) and carries down from there.  These are adjoint_kernel's
+// values bit for bit, as straight-line code without a branch per step, which
+// lets the compiler overlap consecutive steps (adjoint_kernel's per-step
+// branches split the code into blocks it does not schedule across).
+__global__ __launch_bounds__(kRedBlock) void adjoint_blocks_kernel(AdjointArgs a) {
+  constexpr int KB = static_cast<int>(kAnchor);
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const Abc p = to_abc(a.abc);
+  const double dt = a.dt;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  if (i < a.n) {
+    const int64_t n = a.n;
+    const int64_t e = i * a.stride;
+    double l0 = a.lam[0][e], l1 = a.lam[1][e], l2 = a.lam[2][e];
+    const int64_t nseg = (a.nsteps + a.k - 1) / a.k;
+    for (int64_t c = nseg - 1; c >= 0; --c) {
+      // k and nsteps are multiples of KB, so every segment's length is too
+      const int64_t len = min(a.k, a.nsteps - c * a.k);
+      const double* cp = a.tape + (c * kTapeRows) * n + i;
+      for (int64_t q = len / KB - 1; q >= 0; --q) {
+        double x = cp[0], y = cp[n], z = cp[2 * n];
+        Trig3 t{cp[3 * n], cp[4 * n], cp[5 * n], cp[6 * n], cp[7 * n], cp[8 * n]};
+        int r = 1;  // c k is a multiple of kAnchor; (s + 1) mod kAnchor by counting
+        for (int64_t s = c * a.k; s < c * a.k + q * KB; ++s) {
+          rk2_advance<true>(p, dt, r == 0, x, y, z, t);
+          r = r + 1 == KB ? 0 : r + 1;
+        }
+        double bx[KB], by[KB], bz[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) {
+          bx[j] = x;
+          by[j] = y;
+          bz[j] = z;
+          if (j + 1 < KB) rk2_advance_carry(p, dt, x, y, z, t);
+        }
+        Trig3 tj = trig3(bx[KB - 1], by[KB - 1], bz[KB - 1]);
+        rk2_reverse<true>(p, dt, tj, bx[KB - 1], by[KB - 1], bz[KB - 1], l0, l1, l2, g0, g1, g2);
+#pragma unroll
+        for (int j = KB - 2; j >= 0; --j) {
+          tj = trig3_shift<kTierSmall>(tj, bx[j + 1], by[j + 1], bz[j + 1], bx[j] - bx[j + 1],
+                                       by[j] - by[j + 1], bz[j] - bz[j + 1]);
+          rk2_reverse<true>(p, dt, tj, bx[j], by[j], bz[j], l0, l1, l2, g0, g1, g2);
         }
       }
     }
@@ -274,7 +400,10 @@ __global__ __launch_bounds__(kRedBlock) void sqdist_kernel(LossArgs a) {
 hipError_t launch_rk2_forward_ckpt(const CkptArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   const int64_t grid = (a.n + 255) / 256;
-  if (small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C))
+  const bool small = small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C);
+  if (small && a.k % kAnchor == 0 && a.nsteps % kAnchor == 0)
+    hipLaunchKernelGGL(rk2_ckpt_blocks_kernel, dim3(grid), dim3(256), 0, s, a);
+  else if (small)
     hipLaunchKernelGGL(rk2_ckpt_kernel<true>, dim3(grid), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL(rk2_ckpt_kernel<false>, dim3(grid), dim3(256), 0, s, a);
@@ -286,7 +415,10 @@ int64_t adjoint_partials(int64_t n) { return (n + kRedBlock - 1) / kRedBlock; }
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t s) {
   const int64_t grid = adjoint_partials(a.n);
   if (grid > 0) {
-    if (small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C)) {
+    const bool small = small_steps(a.dt, a.abc.A, a.abc.B, a.abc.C);
+    if (small && a.k % kAnchor == 0 && a.nsteps % kAnchor == 0) {
+      hipLaunchKernelGGL(adjoint_blocks_kernel, dim3(grid), dim3(kRedBlock), 0, s, a);
+    } else if (small) {
       if (a.k <= 8)
         hipLaunchKernelGGL((adjoint_kernel<8, true>), dim3(grid), dim3(kRedBlock), 0, s, a);
       else if (a.k <= 20)
