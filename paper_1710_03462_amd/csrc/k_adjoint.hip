@@ -8,9 +8,12 @@
 // indexed by compile-time constants (fully unrolled loops, so the array never
 // touches scratch memory) and sweeps them backwards.  Segments longer than
 // the register array are split into sub-segments, each recomputed from the
-// checkpoint.  Parameter gradients are summed per particle in reverse step
-// order, then over particles by a fixed-shape tree (per workgroup, then one
-// final workgroup), so results are deterministic and do not depend on k.
+// checkpoint.  When k and nsteps are multiples of the renewal interval
+// below, the forward and the adjoint run their steps in blocks of straight-
+// line code without a branch per step.  Parameter gradients are summed per
+// particle in reverse step order, then over particles by a fixed-shape tree
+// (per workgroup, then one final workgroup), so results are deterministic and
+// do not depend on k.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -40,7 +43,7 @@ constexpr int kTapeRows = 9;
 // block of the usual checkpoint interval (20), so that a block that starts
 // at a multiple of it has no renewal inside its recomputation and exactly
 // one, at its first reversed state, in the reverse sweep: such blocks run as
-// straight-line code (adjoint_blocks_kernel).
+// straight-line code (rk2_ckpt_blocks_kernel, adjoint_blocks_kernel).
 constexpr int64_t kAnchor = 20;
 
 // The angle-shift tier of these kernels: SMALL (small_steps holds) or any shift.
