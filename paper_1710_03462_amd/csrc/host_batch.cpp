@@ -478,8 +478,9 @@ extern "C" soax_status soax_batch_tune(soax_batch* b, const char* cache_path) {
         TuneEntry c{bl, pp, bc, 0.0};
         if (!(st = time_shape(c, 3, &c.ms))) timed.push_back(c);
       }
-  // pass 2: the four fastest and the shape in use, 10 launches each, twice in
-  // turn; keep each one's better time
+  // pass 2: the four fastest and the shape in use, 20 launches each, three
+  // times in turn; keep each one's best time (shapes within a few percent of
+  // each other swapped places from run to run with two rounds of 10)
   TuneEntry best = current;
   best.ms = 1e30;
   if (!st) {
@@ -488,10 +489,10 @@ extern "C" soax_status soax_batch_tune(soax_batch* b, const char* cache_path) {
     std::vector<TuneEntry> finalists(timed.begin(), timed.begin() + std::min<size_t>(4, timed.size()));
     finalists.push_back(current);
     for (TuneEntry& c : finalists) c.ms = 1e30;
-    for (int round = 0; round < 2 && !st; ++round)
+    for (int round = 0; round < 3 && !st; ++round)
       for (TuneEntry& c : finalists) {
         double ms = 0.0;
-        if ((st = time_shape(c, 10, &ms))) break;
+        if ((st = time_shape(c, 20, &ms))) break;
         c.ms = std::min(c.ms, ms);
       }
     for (const TuneEntry& c : finalists)
